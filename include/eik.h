@@ -1,0 +1,169 @@
+/*
+ * eik.h -- C ABI of the MI355X (gfx950) eikonal solver library libeik.so.
+ *
+ * The library solves the eikonal equation ||grad phi|| = 1/F (Eq 3) on a
+ * uniform 2D or 3D grid with the improved fast iterative method (Algorithm 2):
+ * an active-list update without the neighbour convergence check (STEP 2),
+ * followed by the error-correction pass that recomputes every node, collects
+ * the ones whose value drops into a remedy list and iterates it to a fixed
+ * point (STEP 3).  The discrete system solved is the first-order Godunov upwind
+ * scheme (Eq 4 in 2D, Eq 6 in 3D) with isotropic spacing h, whose exact local
+ * solve is what Algorithms 1.1 and 1.3 compute.
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers (memory on the current HIP device)
+ *     unless marked "host".  The caller owns every buffer; the library never
+ *     frees caller memory.
+ *   - dims (host) lists the grid extents in C order, last axis fastest (x is
+ *     contiguous): (ny, nx) for ndim = 2, (nz, ny, nx) for ndim = 3.  Flat
+ *     index = ((i0 * d1) + i1) * d2 + i2.  The total node count must be below
+ *     2^31.
+ *   - F, phi and the adjoint arrays share one element type, chosen by
+ *     eik_options.dtype (float32 or float64), and the same shape.
+ *   - F >= 0 and finite.  F = 0 marks a barrier cell (Eq 8): its value is +inf
+ *     unless it is a source.  Unreachable nodes come out as +inf.
+ *   - Sources (host, flat indices) are fixed nodes with given values (default
+ *     0).  Duplicated indices keep their minimum value.
+ *   - Work is enqueued on eik_options.stream (NULL: the default stream).
+ *     Unless EIK_FLAG_ASYNC is set, calls return after the device work has
+ *     completed.
+ *   - Every function returns an eik_status; none aborts.  Validation errors
+ *     are reported before any device work and leave the outputs untouched.
+ *     eik_last_error() gives a per-thread description of the last failure.
+ */
+#ifndef EIK_H_
+#define EIK_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EIK_ABI_VERSION 1
+
+typedef enum {
+    EIK_OK = 0,
+    EIK_ERR_INVALID_ARGUMENT = 1, /* bad shape, spacing, sources, F values, options */
+    EIK_ERR_NO_CONVERGENCE = 2,   /* iteration cap reached; output holds the current
+                                     iterate, an upper bound of the solution */
+    EIK_ERR_OUT_OF_MEMORY = 3,    /* workspace too small or device allocation failed */
+    EIK_ERR_DEVICE = 4,           /* a HIP runtime call failed */
+    EIK_ERR_UNSUPPORTED = 5       /* valid request this build does not implement */
+} eik_status;
+
+typedef enum { EIK_FLOAT32 = 0, EIK_FLOAT64 = 1 } eik_dtype;
+
+typedef enum {
+    /* One lane per list entry over global node lists: the paper's mapping of
+       one thread per active point (Section 3.2). */
+    EIK_VARIANT_NODE_LIST = 0,
+    /* Same node rules scheduled tile by tile: each workgroup stages a tile and
+       its one-cell halo in LDS and runs several inner iterations per launch. */
+    EIK_VARIANT_TILE = 1
+} eik_variant;
+
+enum {
+    /* Synchronous reads per iteration (every update of an iteration sees the
+       previous iteration's values); bitwise reproducible.  Node-list only. */
+    EIK_FLAG_DETERMINISTIC = 1u,
+    /* Diagnostic: return after the update step, skipping the remedy step. */
+    EIK_FLAG_SKIP_REMEDY = 2u,
+    /* Enqueue only: no host synchronisation, no F check, no stats.  The caller
+       must pass a workspace and synchronise the stream itself. */
+    EIK_FLAG_ASYNC = 4u
+};
+
+/* Work counters of one solve (filled when eik_options.stats is non-NULL). */
+typedef struct {
+    int64_t step2_iters;    /* update-step iterations (node-list) or launches (tile) */
+    int64_t step3_iters;    /* remedy iterations / launches */
+    int64_t evals_step2;    /* local-solver evaluations in the update step */
+    int64_t evals_detect;   /* evaluations in the whole-grid remedy detection */
+    int64_t evals_remedy;   /* evaluations in the remedy loop */
+    int64_t remedy_initial; /* nodes (node-list) or tiles (tile) flagged by detection */
+    int64_t max_active;     /* peak active-list length (nodes or tiles) */
+    int64_t launches;       /* kernel launches enqueued */
+} eik_stats;
+
+typedef struct {
+    eik_dtype dtype;           /* element type of F / phi (default float32) */
+    eik_variant variant;       /* default EIK_VARIANT_TILE */
+    int32_t tile[3];           /* tile extents (z, y, x); 0 = library default */
+    int32_t inner_iters;       /* tile variant: inner iterations per launch (0 = default) */
+    int64_t max_iters;         /* cap per loop (0 = default 4 * N + 64) */
+    uint32_t flags;            /* EIK_FLAG_* */
+    const double* source_values; /* host, n_sources entries; NULL -> all 0 */
+    void* workspace;           /* device scratch of workspace_bytes; NULL -> the
+                                  library allocates and frees it per call */
+    size_t workspace_bytes;
+    void* stream;              /* hipStream_t; NULL -> default stream */
+    eik_stats* stats;          /* host, nullable */
+} eik_options;
+
+/* Fill *opt with the defaults listed above.  Never fails. */
+void eik_default_options(eik_options* opt);
+
+/* Device workspace (bytes) eik_solve needs for this shape and options; 0 on
+   invalid arguments.  Host-only; no device work. */
+size_t eik_workspace_size(int32_t ndim, const int64_t* dims, const eik_options* opt);
+
+/*
+ * eik_solve -- Algorithm 2 (STEP 1 initialisation, STEP 2 update, STEP 3
+ * remedy) for the Godunov system of Eq 4 / Eq 6.
+ *   F        device, N elements, speed (>= 0, finite)
+ *   ndim     2 or 3; dims (host) as above; h > 0 finite grid spacing
+ *   sources  host, n_sources >= 1 flat indices in [0, N)
+ *   eps      >= 0; a node counts as converged when phi - phi~ <= eps and is
+ *            flagged by the remedy when phi~ < phi - eps (0 = exact equality)
+ *   phi_out  device, N elements, receives the solution
+ *   opt      nullable -> defaults
+ * Errors: EIK_ERR_INVALID_ARGUMENT (arguments, or F negative / non-finite as
+ * found on the device), EIK_ERR_NO_CONVERGENCE, EIK_ERR_OUT_OF_MEMORY,
+ * EIK_ERR_DEVICE.
+ */
+eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
+                     const int64_t* sources, int64_t n_sources, double eps,
+                     void* phi_out, const eik_options* opt);
+
+/*
+ * eik_apply_local -- one dense pass of the local solver: out_i = G_i(phi),
+ * the exact root of Eq 4 / Eq 6 at node i given its neighbours' values
+ * (out-of-grid neighbours +inf), for every node including sources.  This is
+ * the "calculate phi~ for all grid points" pass of STEP 3.
+ *   F, phi device inputs (N elements); out device output (N elements, may not
+ *   alias phi).  opt: dtype and stream are used.
+ */
+eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
+                           double h, void* out, const eik_options* opt);
+
+/*
+ * eik_adjoint -- gradient of a loss L(phi) with respect to F at a converged
+ * solution phi of eik_solve (same F, h, sources).  At the solution each
+ * reached non-source node satisfies sum_k w_ik^2 = (h/F_i)^2 over its upwind
+ * axes (w_ik = phi_i - phi_upwind); the linearised system is transposed and
+ * solved downwind-to-upwind:
+ *   lambda = dL/dphi + M^T lambda,  M_ij = w_ij / W_i,  W_i = sum_k w_ik,
+ *   dL/dF_i = -lambda_i (h/F_i)^2 / (F_i W_i);  0 at sources and +inf nodes.
+ *   dL_dphi device input (N), dL_dF_out device output (N).
+ * Errors as eik_solve.
+ */
+eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
+                       double h, const int64_t* sources, int64_t n_sources,
+                       const void* dL_dphi, void* dL_dF_out, const eik_options* opt);
+
+/* Human-readable name of a status code (static storage). */
+const char* eik_status_string(eik_status s);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char* eik_last_error(void);
+
+/* EIK_ABI_VERSION of the loaded library. */
+int32_t eik_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIK_H_ */

@@ -63,6 +63,8 @@ def _load():
         lib.eo_godunov_bisect.argtypes = [i, P, d]
         lib.eo_apply_local.restype = i
         lib.eo_apply_local.argtypes = [i, P, d, P, P, P]
+        lib.eo_apply_local_f.restype = i
+        lib.eo_apply_local_f.argtypes = [i, P, d, P, P, P]
         lib.eo_fmm.restype = i
         lib.eo_fmm.argtypes = [i, P, d, P, P, P, i64, P, P, P]
         lib.eo_fsm.restype = i
@@ -108,8 +110,17 @@ def godunov_bisect(a: Sequence[float], H: float) -> float:
     return float(_load().eo_godunov_bisect(len(arr), _ptr(arr), float(H)))
 
 
-def apply_local(F, h: float, phi) -> np.ndarray:
-    """G_i(phi) at every node (float64)."""
+def apply_local(F, h: float, phi, dtype=np.float64) -> np.ndarray:
+    """G_i(phi) at every node, in float64 (default) or float32 arithmetic."""
+    if np.dtype(dtype) == np.float32:
+        F32 = np.ascontiguousarray(np.asarray(F), dtype=np.float32)
+        p32 = np.ascontiguousarray(np.asarray(phi), dtype=np.float32)
+        o32 = np.empty_like(F32)
+        dims = np.asarray(F32.shape, dtype=np.int64)
+        rc = _load().eo_apply_local_f(F32.ndim, _ptr(dims), float(h), _ptr(F32), _ptr(p32), _ptr(o32))
+        if rc:
+            raise ValueError("eo_apply_local_f failed: %d" % rc)
+        return o32
     F64 = np.ascontiguousarray(np.asarray(F), dtype=np.float64)
     p = np.ascontiguousarray(np.asarray(phi), dtype=np.float64)
     out = np.empty_like(F64)

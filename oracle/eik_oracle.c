@@ -604,3 +604,18 @@ int eo_adjoint(int ndim, const int64_t* dims, double h, const double* F,
     if (!lambda_out) free(lam);
     return EO_OK;
 }
+
+/* G_i(phi) for every node in float32 arithmetic (phi, F float32 values) */
+int eo_apply_local_f(int ndim, const int64_t* dims, double h, const float* F,
+                     const float* phi, float* out) {
+    grid_t g;
+    if (grid_init(&g, ndim, dims)) return EO_BAD;
+    float a[3];
+    const float hf = (float)h;
+    for (int64_t i = 0; i < g.n; ++i) {
+        axis_mins_f(&g, phi, i, a);
+        float Hi = F[i] > 0.0f ? hf / F[i] : INFINITY;
+        out[i] = eo_godunov_f(g.nd, a, Hi);
+    }
+    return EO_OK;
+}

@@ -1,0 +1,287 @@
+"""MI355X (gfx950) eikonal solver: the improved fast iterative method.
+
+Thin Python binding of ``libeik.so`` (C ABI in ``include/eik.h``).  It only
+marshals arguments: every step of a solve runs in the library's HIP kernels.
+PyTorch provides device memory and the stream.  If the library is not built
+the binding raises; there is no fallback path.
+
+Functions mirror the C entry points:
+
+* ``eik_solve``        Algorithm 2 (initialisation, update, remedy).
+* ``eik_apply_local``  one dense pass of the exact Godunov local solve.
+* ``eik_adjoint``      dL/dF at a converged solution.
+* ``eik_workspace_size``, ``eik_status_string``, ``eik_abi_version``.
+
+``solve`` / ``apply_local`` / ``adjoint`` are the tensor-level wrappers and
+``EikonalFn`` the autograd function built on ``eik_solve`` + ``eik_adjoint``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple, Union
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeik.so")
+
+EIK_OK = 0
+EIK_ERR_INVALID_ARGUMENT = 1
+EIK_ERR_NO_CONVERGENCE = 2
+EIK_ERR_OUT_OF_MEMORY = 3
+EIK_ERR_DEVICE = 4
+EIK_ERR_UNSUPPORTED = 5
+
+EIK_FLOAT32 = 0
+EIK_FLOAT64 = 1
+EIK_VARIANT_NODE_LIST = 0
+EIK_VARIANT_TILE = 1
+EIK_FLAG_DETERMINISTIC = 1
+EIK_FLAG_SKIP_REMEDY = 2
+EIK_FLAG_ASYNC = 4
+
+VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
+            "tile": EIK_VARIANT_TILE}
+
+# Entry points declared in include/eik.h
+EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
+           "eik_adjoint", "eik_status_string", "eik_last_error", "eik_abi_version")
+
+
+class EikStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
+        "remedy_initial", "max_active", "launches")]
+
+    def to_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class EikOptions(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int),
+        ("variant", ctypes.c_int),
+        ("tile", ctypes.c_int32 * 3),
+        ("inner_iters", ctypes.c_int32),
+        ("max_iters", ctypes.c_int64),
+        ("flags", ctypes.c_uint32),
+        ("source_values", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+        ("stats", ctypes.POINTER(EikStats)),
+    ]
+
+
+class EikError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{_status_name(status)}: {detail}")
+
+
+_lib = None
+
+
+def _status_name(s: int) -> str:
+    try:
+        return _load().eik_status_string(s).decode()
+    except Exception:  # pragma: no cover
+        return f"status {s}"
+
+
+def _load():
+    """Load libeik.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2106_15869_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    OP = ctypes.POINTER(EikOptions)
+    lib.eik_default_options.restype = None
+    lib.eik_default_options.argtypes = [OP]
+    lib.eik_workspace_size.restype = ctypes.c_size_t
+    lib.eik_workspace_size.argtypes = [i32, P, OP]
+    lib.eik_solve.restype = ctypes.c_int
+    lib.eik_solve.argtypes = [P, i32, P, d, P, i64, d, P, OP]
+    lib.eik_apply_local.restype = ctypes.c_int
+    lib.eik_apply_local.argtypes = [P, P, i32, P, d, P, OP]
+    lib.eik_adjoint.restype = ctypes.c_int
+    lib.eik_adjoint.argtypes = [P, P, i32, P, d, P, i64, P, P, OP]
+    lib.eik_status_string.restype = ctypes.c_char_p
+    lib.eik_status_string.argtypes = [ctypes.c_int]
+    lib.eik_last_error.restype = ctypes.c_char_p
+    lib.eik_last_error.argtypes = []
+    lib.eik_abi_version.restype = i32
+    lib.eik_abi_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def _check(rc: int):
+    if rc != EIK_OK:
+        raise EikError(rc, _load().eik_last_error().decode())
+
+
+def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[Sequence[int]] = None,
+                 inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
+                 skip_remedy: bool = False, async_: bool = False) -> EikOptions:
+    o = EikOptions()
+    _load().eik_default_options(ctypes.byref(o))
+    if dtype is not None:
+        o.dtype = dtype
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    if tile is not None:
+        t = list(tile)
+        t = [0] * (3 - len(t)) + t if len(t) < 3 else t
+        for k in range(3):
+            o.tile[k] = int(t[k])
+    o.inner_iters = int(inner_iters)
+    o.max_iters = int(max_iters)
+    o.flags = ((EIK_FLAG_DETERMINISTIC if deterministic else 0) |
+               (EIK_FLAG_SKIP_REMEDY if skip_remedy else 0) |
+               (EIK_FLAG_ASYNC if async_ else 0))
+    return o
+
+
+def _dims(shape) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(list(shape), dtype=np.int64))
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def eik_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] = None) -> int:
+    dims = _dims(shape)
+    return int(_load().eik_workspace_size(len(dims), _np_ptr(dims),
+                                          ctypes.byref(opt) if opt is not None else None))
+
+
+def eik_status_string(status: int) -> str:
+    return _load().eik_status_string(status).decode()
+
+
+def eik_abi_version() -> int:
+    return int(_load().eik_abi_version())
+
+
+# ---------------------------------------------------------------------------
+# tensor-level wrappers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return EIK_FLOAT32
+    if t.dtype == torch.float64:
+        return EIK_FLOAT64
+    raise TypeError("F must be float32 or float64")
+
+
+def _check_device_tensor(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _sources_array(sources, shape) -> np.ndarray:
+    arr = np.asarray(sources.cpu() if hasattr(sources, "cpu") else sources)
+    if arr.ndim == 2 and arr.shape[1] == len(shape):
+        arr = np.ravel_multi_index(tuple(arr.T.astype(np.int64)), tuple(shape))
+    return np.ascontiguousarray(arr.astype(np.int64).ravel())
+
+
+def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = "tile",
+          source_values=None, deterministic: bool = False, skip_remedy: bool = False,
+          tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
+          out=None, workspace=None, stats: bool = False, stream=None):
+    """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
+
+    sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
+    (and a stats dict when stats=True)."""
+    torch = _torch()
+    _check_device_tensor(F, "F")
+    if F.dim() not in (2, 3):
+        raise ValueError("F must be 2D or 3D")
+    opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
+                       skip_remedy)
+    dims = _dims(F.shape)
+    src = _sources_array(sources, F.shape)
+    vals = None
+    if source_values is not None:
+        vals = np.ascontiguousarray(np.asarray(source_values, dtype=np.float64).ravel())
+        if vals.shape != src.shape:
+            raise ValueError("source_values must match sources")
+        opt.source_values = vals.ctypes.data
+    phi = out if out is not None else torch.empty_like(F)
+    _check_device_tensor(phi, "out")
+    need = eik_workspace_size(F.shape, opt)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    elif workspace.numel() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    st = EikStats()
+    opt.stats = ctypes.pointer(st)
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    with torch.cuda.device(F.device):
+        rc = _load().eik_solve(F.data_ptr(), F.dim(), _np_ptr(dims), float(h), _np_ptr(src),
+                               len(src), float(eps), phi.data_ptr(), ctypes.byref(opt))
+    _check(rc)
+    return (phi, st.to_dict()) if stats else phi
+
+
+def apply_local(F, phi, h: float, out=None):
+    """out_i = G_i(phi): the exact Godunov local solve at every node."""
+    torch = _torch()
+    _check_device_tensor(F, "F")
+    _check_device_tensor(phi, "phi")
+    if phi.shape != F.shape or phi.dtype != F.dtype:
+        raise ValueError("phi must match F in shape and dtype")
+    opt = make_options(_dtype_code(F))
+    opt.stream = torch.cuda.current_stream(F.device).cuda_stream
+    res = out if out is not None else torch.empty_like(F)
+    dims = _dims(F.shape)
+    with torch.cuda.device(F.device):
+        rc = _load().eik_apply_local(F.data_ptr(), phi.data_ptr(), F.dim(), _np_ptr(dims), float(h),
+                                     res.data_ptr(), ctypes.byref(opt))
+    _check(rc)
+    return res
+
+
+def adjoint(F, phi, h: float, sources, dL_dphi, out=None):
+    """dL/dF at the converged solution phi (same F, h, sources)."""
+    torch = _torch()
+    for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
+        _check_device_tensor(t, n)
+        if t.shape != F.shape or t.dtype != F.dtype:
+            raise ValueError(f"{n} must match F in shape and dtype")
+    opt = make_options(_dtype_code(F))
+    opt.stream = torch.cuda.current_stream(F.device).cuda_stream
+    res = out if out is not None else torch.empty_like(F)
+    dims = _dims(F.shape)
+    src = _sources_array(sources, F.shape)
+    with torch.cuda.device(F.device):
+        rc = _load().eik_adjoint(F.data_ptr(), phi.data_ptr(), F.dim(), _np_ptr(dims), float(h),
+                                 _np_ptr(src), len(src), dL_dphi.data_ptr(), res.data_ptr(),
+                                 ctypes.byref(opt))
+    _check(rc)
+    return res

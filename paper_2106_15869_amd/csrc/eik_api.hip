@@ -1,0 +1,358 @@
+// C ABI of libeik.so: argument validation, workspace carving and the host
+// driver that enqueues Algorithm 2's loops without a host round trip per
+// iteration.  The loops are enqueued in chunks; the list length after a chunk
+// is copied to pinned host memory and inspected while the next chunk already
+// runs, so the device never waits for the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/eik.h"
+#include "eik_internal.hpp"
+#include "eik_host.hpp"
+#include "eik_tile.hpp"
+
+#define EIK_API extern "C" __attribute__((visibility("default")))
+
+namespace eik {
+
+thread_local std::string g_last_error;
+
+struct Problem {
+    GridDims g;
+    int64_t n;
+};
+
+static eik_status check_shape(int32_t ndim, const int64_t* dims, Problem& P) {
+    if (ndim != 2 && ndim != 3) return fail(EIK_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+    if (!dims) return fail(EIK_ERR_INVALID_ARGUMENT, "dims is NULL");
+    int64_t n = 1;
+    for (int k = 0; k < ndim; ++k) {
+        if (dims[k] < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every dim must be >= 1");
+        if (dims[k] > (int64_t(1) << 31)) return fail(EIK_ERR_INVALID_ARGUMENT, "dim too large");
+        n *= dims[k];
+        if (n >= (int64_t(1) << 31)) return fail(EIK_ERR_INVALID_ARGUMENT, "grid must have < 2^31 nodes");
+    }
+    P.n = n;
+    P.g.nd = ndim;
+    P.g.n = static_cast<int>(n);
+    if (ndim == 2) {
+        P.g.nz = 1;
+        P.g.ny = static_cast<int>(dims[0]);
+        P.g.nx = static_cast<int>(dims[1]);
+    } else {
+        P.g.nz = static_cast<int>(dims[0]);
+        P.g.ny = static_cast<int>(dims[1]);
+        P.g.nx = static_cast<int>(dims[2]);
+    }
+    return EIK_OK;
+}
+
+static eik_options resolve(const eik_options* opt) {
+    eik_options o;
+    eik_default_options(&o);
+    if (opt) o = *opt;
+    return o;
+}
+
+static eik_status check_options(const eik_options& o) {
+    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "unknown dtype");
+    if (o.variant != EIK_VARIANT_NODE_LIST && o.variant != EIK_VARIANT_TILE)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "unknown variant");
+    if (o.max_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "max_iters must be >= 0");
+    if (o.inner_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "inner_iters must be >= 0");
+    if (o.flags & ~7u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
+    if ((o.flags & EIK_FLAG_DETERMINISTIC) && o.variant != EIK_VARIANT_NODE_LIST)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_FLAG_DETERMINISTIC needs the node-list variant");
+    if ((o.flags & EIK_FLAG_ASYNC) && (!o.workspace || o.max_iters == 0))
+        return fail(EIK_ERR_INVALID_ARGUMENT,
+                    "EIK_FLAG_ASYNC needs a caller workspace and an explicit max_iters");
+    if (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) & 255u))
+        return fail(EIK_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    for (int k = 0; k < 3; ++k)
+        if (o.tile[k] < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "tile extents must be >= 0");
+    return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+struct NodeWs {
+    Ctl* ctl;
+    uint8_t* lab;
+    uint32_t* stamp;
+    int* list[2];
+    void* vals;
+    size_t bytes;
+};
+
+static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
+    NodeWs w{};
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + b, 256);
+        return p;
+    };
+    w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
+    w.stamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(n)));
+    w.list[0] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(n)));
+    w.list[1] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(n)));
+    w.vals = det ? take(esz * static_cast<size_t>(n)) : nullptr;
+    w.bytes = off;
+    return w;
+}
+
+static size_t elem_size(eik_dtype d) { return d == EIK_FLOAT64 ? 8 : 4; }
+
+static size_t workspace_bytes(const Problem& P, const eik_options& o) {
+    if (o.variant == EIK_VARIANT_TILE) return tile_workspace_bytes(P.g, o);
+    return node_layout(nullptr, P.n, elem_size(o.dtype), (o.flags & EIK_FLAG_DETERMINISTIC) != 0).bytes;
+}
+
+// Scratch owned by the library when the caller passes no workspace.
+struct OwnedWs {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    ~OwnedWs() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+};
+
+std::vector<std::pair<int, double>> dedupe_sources(const int64_t* src, const double* val, int64_t ns) {
+    std::vector<std::pair<int, double>> v;
+    v.reserve(static_cast<size_t>(ns));
+    for (int64_t k = 0; k < ns; ++k) v.emplace_back(static_cast<int>(src[k]), val ? val[k] : 0.0);
+    std::sort(v.begin(), v.end());
+    std::vector<std::pair<int, double>> out;
+    for (auto& e : v)
+        if (out.empty() || out.back().first != e.first) out.push_back(e);
+    return out;  // sorted by (index, value): the first of each index has the minimum value
+}
+
+eik_status check_sources(const Problem& P, const int64_t* sources, int64_t n_sources,
+                         const double* values) {
+    if (n_sources < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "need at least one source");
+    if (!sources) return fail(EIK_ERR_INVALID_ARGUMENT, "sources is NULL");
+    for (int64_t k = 0; k < n_sources; ++k) {
+        if (sources[k] < 0 || sources[k] >= P.n)
+            return fail(EIK_ERR_INVALID_ARGUMENT, "source index out of range");
+        if (values && !std::isfinite(values[k]))
+            return fail(EIK_ERR_INVALID_ARGUMENT, "source values must be finite");
+    }
+    return EIK_OK;
+}
+
+static int list_blocks() { return 512; }
+
+template <typename T>
+static eik_status solve_nodelist(const Problem& P, const T* F, double h, double eps,
+                                 const std::vector<std::pair<int, double>>& src, T* phi,
+                                 const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
+    const bool det = (o.flags & EIK_FLAG_DETERMINISTIC) != 0;
+    const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
+    NodeWs w = node_layout(ws, P.n, sizeof(T), det);
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * P.n + 64;
+    int64_t launched = 0;
+
+    HIP_TRY(launch_ctl_init(w.ctl, s));
+    HIP_TRY(launch_init<T>(F, phi, w.lab, w.stamp, P.g.n, w.ctl, s));
+    launched += 2;
+    // STEP 1: fixed boundary values, then their FAR neighbours become active
+    std::vector<SrcBatch<T>> batches;
+    for (size_t k = 0; k < src.size(); k += kMaxSrcBatch) {
+        SrcBatch<T> b{};
+        b.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, src.size() - k));
+        for (int j = 0; j < b.count; ++j) {
+            b.idx[j] = src[k + j].first;
+            b.val[j] = static_cast<T>(src[k + j].second);
+        }
+        batches.push_back(b);
+    }
+    for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
+    for (auto& b : batches)
+        HIP_TRY(launch_seed_active<T>(P.g, F, w.lab, b, w.list[0], &w.ctl->cnt[0], s));
+    launched += 2 * static_cast<int64_t>(batches.size());
+
+    const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
+    auto iter_args = [&](int64_t t, bool first) {
+        NodeIter<T> a{};
+        a.F = F;
+        a.phi = phi;
+        a.lab = w.lab;
+        a.stamp = w.stamp;
+        a.vals = static_cast<T*>(w.vals);
+        a.list_cur = w.list[t & 1];
+        a.list_next = w.list[(t + 1) & 1];
+        a.cnt_cur = &w.ctl->cnt[t % 3];
+        a.cnt_next = &w.ctl->cnt[(t + 1) % 3];
+        a.cnt_zero = &w.ctl->cnt[(t + 2) % 3];
+        a.ctl = w.ctl;
+        a.tag_slot = static_cast<int>(t & 1);
+        a.first = first ? 1 : 0;
+        return a;
+    };
+    auto counter = [&](int64_t t) { return &w.ctl->cnt[t % 3]; };
+
+    // STEP 2
+    eik_status rc = run_loop(
+        [&](int64_t t) { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, list_blocks(), s); },
+        counter, cap, async, s, &launched);
+    if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
+        // STEP 3a: whole-grid check
+        HIP_TRY(launch_reset_counters(w.ctl, s));
+        HIP_TRY(launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.list[0], &w.ctl->cnt[0], s));
+        launched += 2;
+        // STEP 3b: remedy loop
+        rc = run_loop(
+            [&](int64_t t) { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, list_blocks(), s); },
+            counter, cap, async, s, &launched);
+    }
+    if (async) return rc;
+    HostSlots& hs = host_slots();
+    HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
+    if (st) {
+        st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
+        st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
+        st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
+        st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : P.n - static_cast<int64_t>(src.size());
+        st->evals_remedy = static_cast<int64_t>(hs.ctl->evals_rem);
+        st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
+        st->max_active = static_cast<int64_t>(hs.ctl->max_active);
+        st->launches = launched;
+    }
+    return rc;
+}
+
+}  // namespace eik
+
+using namespace eik;
+
+EIK_API void eik_default_options(eik_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->dtype = EIK_FLOAT32;
+    opt->variant = EIK_VARIANT_TILE;
+}
+
+EIK_API size_t eik_workspace_size(int32_t ndim, const int64_t* dims, const eik_options* opt) {
+    Problem P;
+    if (check_shape(ndim, dims, P) != EIK_OK) return 0;
+    eik_options o = resolve(opt);
+    if (check_options(o) != EIK_OK) {
+        // ASYNC without a workspace is still a valid size query
+        eik_options q = o;
+        q.flags &= ~static_cast<uint32_t>(EIK_FLAG_ASYNC);
+        q.workspace = nullptr;
+        if (check_options(q) != EIK_OK) return 0;
+    }
+    return workspace_bytes(P, o);
+}
+
+EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
+                             const int64_t* sources, int64_t n_sources, double eps, void* phi_out,
+                             const eik_options* opt) {
+    g_last_error.clear();
+    Problem P;
+    eik_status rc = check_shape(ndim, dims, P);
+    if (rc) return rc;
+    eik_options o = resolve(opt);
+    if ((rc = check_options(o))) return rc;
+    if (!F || !phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "F and phi_out must be non-NULL");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(EIK_ERR_INVALID_ARGUMENT, "eps must be finite and >= 0");
+    if ((rc = check_sources(P, sources, n_sources, o.source_values))) return rc;
+    if (F == phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_out must not alias F");
+
+    const size_t need = workspace_bytes(P, o);
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    OwnedWs owned;
+    char* ws = static_cast<char*>(o.workspace);
+    if (ws) {
+        if (o.workspace_bytes < need) return fail(EIK_ERR_OUT_OF_MEMORY, "workspace too small");
+    } else {
+        if (hipMallocAsync(&owned.p, need, s) != hipSuccess)
+            return fail(EIK_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        owned.s = s;
+        ws = static_cast<char*>(owned.p);
+    }
+    auto src = dedupe_sources(sources, o.source_values, n_sources);
+    if (o.variant == EIK_VARIANT_TILE) {
+        if (o.dtype == EIK_FLOAT64)
+            return solve_tile<double>(P.g, static_cast<const double*>(F), h, eps, src,
+                                      static_cast<double*>(phi_out), o, ws, s, o.stats);
+        return solve_tile<float>(P.g, static_cast<const float*>(F), h, eps, src,
+                                 static_cast<float*>(phi_out), o, ws, s, o.stats);
+    }
+    if (o.dtype == EIK_FLOAT64)
+        return solve_nodelist<double>(P, static_cast<const double*>(F), h, eps, src,
+                                      static_cast<double*>(phi_out), o, ws, s, o.stats);
+    return solve_nodelist<float>(P, static_cast<const float*>(F), h, eps, src,
+                                 static_cast<float*>(phi_out), o, ws, s, o.stats);
+}
+
+EIK_API eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim,
+                                   const int64_t* dims, double h, void* out,
+                                   const eik_options* opt) {
+    g_last_error.clear();
+    Problem P;
+    eik_status rc = check_shape(ndim, dims, P);
+    if (rc) return rc;
+    eik_options o = resolve(opt);
+    if ((rc = check_options(o))) return rc;
+    if (!F || !phi || !out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
+    if (out == phi || out == F) return fail(EIK_ERR_INVALID_ARGUMENT, "out must not alias the inputs");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    if (o.dtype == EIK_FLOAT64)
+        HIP_TRY(launch_apply_local<double>(P.g, static_cast<const double*>(F),
+                                           static_cast<const double*>(phi), h,
+                                           static_cast<double*>(out), s));
+    else
+        HIP_TRY(launch_apply_local<float>(P.g, static_cast<const float*>(F),
+                                          static_cast<const float*>(phi), static_cast<float>(h),
+                                          static_cast<float*>(out), s));
+    if (!(o.flags & EIK_FLAG_ASYNC)) HIP_TRY(hipStreamSynchronize(s));
+    return EIK_OK;
+}
+
+EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
+                               double h, const int64_t* sources, int64_t n_sources,
+                               const void* dL_dphi, void* dL_dF_out, const eik_options* opt) {
+    g_last_error.clear();
+    Problem P;
+    eik_status rc = check_shape(ndim, dims, P);
+    if (rc) return rc;
+    eik_options o = resolve(opt);
+    if ((rc = check_options(o))) return rc;
+    if (!F || !phi || !dL_dphi || !dL_dF_out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+    if ((rc = check_sources(P, sources, n_sources, nullptr))) return rc;
+    return fail(EIK_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+EIK_API const char* eik_status_string(eik_status s) {
+    switch (s) {
+        case EIK_OK: return "EIK_OK";
+        case EIK_ERR_INVALID_ARGUMENT: return "EIK_ERR_INVALID_ARGUMENT";
+        case EIK_ERR_NO_CONVERGENCE: return "EIK_ERR_NO_CONVERGENCE";
+        case EIK_ERR_OUT_OF_MEMORY: return "EIK_ERR_OUT_OF_MEMORY";
+        case EIK_ERR_DEVICE: return "EIK_ERR_DEVICE";
+        case EIK_ERR_UNSUPPORTED: return "EIK_ERR_UNSUPPORTED";
+    }
+    return "EIK_UNKNOWN_STATUS";
+}
+
+EIK_API const char* eik_last_error(void) { return g_last_error.c_str(); }
+
+EIK_API int32_t eik_abi_version(void) { return EIK_ABI_VERSION; }

@@ -1,0 +1,195 @@
+// Device-side building blocks of the gfx950 eikonal kernels: grid geometry,
+// the exact Godunov local solve, node labels and wave64 list compaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eik {
+
+// Node labels (one byte per node).  FAR: never reached; ACTIVE: in the update
+// list; CONV: converged in the update step (joins the Source set); FIXED: a
+// given boundary value (Algorithm 2, STEP 1).
+enum : uint32_t { L_FAR = 0u, L_ACTIVE = 1u, L_CONV = 2u, L_FIXED = 3u };
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+
+template <typename T> __device__ __forceinline__ T pos_inf();
+template <> __device__ __forceinline__ float pos_inf<float>() { return __builtin_huge_valf(); }
+template <> __device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
+
+__device__ __forceinline__ float dev_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dev_sqrt(double x) { return __builtin_sqrt(x); }
+
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
+
+// Grid extents; 2D grids use nz = 1.  Node count < 2^31.
+struct Grid {
+    int nx, ny, nz;
+    int n;
+    int sxy;  // nx * ny
+};
+
+template <int ND>
+__device__ __forceinline__ void decode(const Grid& g, int i, int& x, int& y, int& z) {
+    x = i % g.nx;
+    if (ND == 2) {
+        y = i / g.nx;
+        z = 0;
+    } else {
+        int t = i / g.nx;
+        y = t % g.ny;
+        z = t / g.ny;
+    }
+}
+
+// Exact solution of sum_k ((phi - a_k)^+)^2 = H^2 over the ND per-axis minima
+// (Eq 4 in 2D, Eq 6 in 3D; the quantity Algorithms 1.1 and 1.3 compute).
+// Written relative to the smallest minimum (b_k = a_k - a_1) so that large
+// arrival times do not cancel; an axis joins while the running root still
+// exceeds its minimum.  Returns +inf when nothing upwind is finite or H = +inf.
+template <typename T, int ND>
+__device__ __forceinline__ T godunov(T a0, T a1, T a2, T H) {
+    const T inf = pos_inf<T>();
+    // ascending sort
+    T lo = tmin(a0, a1), hi = a0 < a1 ? a1 : a0;
+    a0 = lo;
+    a1 = hi;
+    if (ND == 3) {
+        T m2 = a2;
+        if (m2 < a1) {
+            a2 = a1;
+            a1 = m2;
+            if (a1 < a0) {
+                T t = a0;
+                a0 = a1;
+                a1 = t;
+            }
+        }
+    }
+    if (!(H < inf) || !(a0 < inf)) return inf;
+    T phi = a0 + H;
+    if (!(phi > a1)) return phi;
+    T b = a1 - a0;
+    T S = b;
+    T Q = b * b;
+    T HH = H * H;
+    T disc = S * S - T(2) * (Q - HH);
+    disc = disc < T(0) ? T(0) : disc;
+    phi = a0 + (S + dev_sqrt(disc)) / T(2);
+    if (ND == 3) {
+        if (!(phi > a2)) return phi;
+        b = a2 - a0;
+        S = S + b;
+        Q = Q + b * b;
+        disc = S * S - T(3) * (Q - HH);
+        disc = disc < T(0) ? T(0) : disc;
+        phi = a0 + (S + dev_sqrt(disc)) / T(3);
+    }
+    return phi;
+}
+
+// H_i = h / F_i, +inf for a barrier cell.
+template <typename T> __device__ __forceinline__ T cell_H(T h, T f) {
+    return f > T(0) ? h / f : pos_inf<T>();
+}
+
+// G_i(phi) from global memory.
+template <typename T, int ND>
+__device__ __forceinline__ T eval_node(const T* phi, const T* F, const Grid& g, int i, int x, int y,
+                                       int z, T h) {
+    const T inf = pos_inf<T>();
+    T ax = inf, ay = inf, az = inf;
+    if (x > 0) ax = phi[i - 1];
+    if (x + 1 < g.nx) ax = tmin(ax, phi[i + 1]);
+    if (y > 0) ay = phi[i - g.nx];
+    if (y + 1 < g.ny) ay = tmin(ay, phi[i + g.nx]);
+    if (ND == 3) {
+        if (z > 0) az = phi[i - g.sxy];
+        if (z + 1 < g.nz) az = tmin(az, phi[i + g.sxy]);
+    }
+    if (ND == 2) return godunov<T, 2>(ay, ax, inf, cell_H(h, F[i]));
+    return godunov<T, 3>(az, ay, ax, cell_H(h, F[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Byte labels packed four to a 32-bit word; transitions use word atomics so
+// that concurrent updates of neighbouring bytes never overwrite each other.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t label_get(const uint8_t* lab, int i) { return lab[i]; }
+
+__device__ __forceinline__ bool label_cas(uint8_t* lab, int i, uint32_t expect, uint32_t desired) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(lab + (i & ~3));
+    const int sh = (i & 3) * 8;
+    uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (((old >> sh) & 0xffu) != expect) return false;
+        uint32_t nw = (old & ~(0xffu << sh)) | (desired << sh);
+        uint32_t prev = atomicCAS(w, old, nw);
+        if (prev == old) return true;
+        old = prev;
+    }
+}
+
+// Add a signed delta to one byte label (caller guarantees no carry/borrow).
+__device__ __forceinline__ void label_add(uint8_t* lab, int i, int delta) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(lab + (i & ~3));
+    const int sh = (i & 3) * 8;
+    atomicAdd(w, static_cast<uint32_t>(delta) << sh);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Append `c` (<= MAXC) items per lane to list[*cnt ...] with one atomic per
+// wave.  Must be called by every lane of the wave (c may be 0).
+template <int MAXC>
+__device__ __forceinline__ void wave_append(int* list, int* cnt, const int (&items)[MAXC], int c) {
+    int incl = wave_incl_scan(c);
+    int total = __shfl(incl, 63, 64);
+    int base = 0;
+    if (total > 0) {
+        if (lane_id() == 63) base = atomicAdd(cnt, total);
+        base = __shfl(base, 63, 64);
+    }
+    int pos = base + incl - c;
+#pragma unroll
+    for (int j = 0; j < MAXC; ++j)
+        if (j < c) list[pos + j] = items[j];
+}
+
+// Single item per lane (flag), one atomic per wave: ballot + mbcnt.
+__device__ __forceinline__ void wave_append1(int* list, int* cnt, int item, bool flag) {
+    uint64_t m = __ballot(flag);
+    if (m == 0) return;
+    int n = __popcll(m);
+    int base = 0;
+    int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    if (lane_id() == leader) base = atomicAdd(cnt, n);
+    base = __shfl(base, leader, 64);
+    if (flag) {
+        uint32_t lo = static_cast<uint32_t>(m), hi = static_cast<uint32_t>(m >> 32);
+        int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        list[base + rank] = item;
+    }
+}
+
+// 64-bit counter add
+__device__ __forceinline__ void add64(unsigned long long* p, unsigned long long v) {
+    if (v) atomicAdd(p, v);
+}
+
+}  // namespace eik

@@ -1,0 +1,81 @@
+// Host/device shared definitions of the eikonal library: control block,
+// kernel argument packs and the launchers the C ABI driver calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace eik {
+
+struct Grid;
+
+// Device control block (lives in the workspace).
+struct Ctl {
+    int cnt[4];       // rotating list counters: iteration t reads cnt[t%3]
+    int err;          // bit 0: F negative or not finite
+    int tag[2];       // remedy stamp tags, alternating by iteration parity
+    int pad;
+    unsigned long long iters2, iters3, evals2, evals_det, evals_rem, remedy_init, max_active;
+    unsigned long long pad2;
+};
+
+constexpr int kMaxSrcBatch = 64;
+
+template <typename T>
+struct SrcBatch {
+    int count;
+    int idx[kMaxSrcBatch];
+    T val[kMaxSrcBatch];
+};
+
+// Pointers a node-list iteration needs; the driver rotates lists and
+// counters by iteration parity: list t&1 -> (t+1)&1, cnt t%3 -> (t+1)%3.
+template <typename T>
+struct NodeIter {
+    const T* F;
+    T* phi;
+    uint8_t* lab;
+    uint32_t* stamp;
+    T* vals;           // per-entry values (synchronous-read mode)
+    const int* list_cur;
+    int* list_next;
+    int* cnt_cur;
+    int* cnt_next;
+    int* cnt_zero;
+    Ctl* ctl;
+    int tag_slot;      // parity of this iteration (remedy stamp tag slot)
+    int first;         // first iteration of its loop
+};
+
+struct GridDims {
+    int nd;
+    int nx, ny, nz;
+    int n;
+};
+
+// ---- launchers implemented in eik_nodelist.hip (T = float/double, ND = 2/3)
+template <typename T>
+hipError_t launch_init(const T* F, T* phi, uint8_t* lab, uint32_t* stamp, int n, Ctl* ctl,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_seed(T* phi, uint8_t* lab, const SrcBatch<T>& b, hipStream_t s);
+template <typename T>
+hipError_t launch_seed_active(const GridDims& g, const T* F, uint8_t* lab, const SrcBatch<T>& b,
+                              int* list, int* cnt, hipStream_t s);
+template <typename T>
+hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
+                        int grid_blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, T h, T eps,
+                         int* list, int* cnt, hipStream_t s);
+template <typename T>
+hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
+                         int grid_blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
+                              hipStream_t s);
+hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s);
+hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
+
+}  // namespace eik

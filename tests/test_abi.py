@@ -1,0 +1,144 @@
+"""Host-side checks of the C ABI (no device work): the library loads, exports
+every entry point include/eik.h declares, sizes workspaces and rejects invalid
+arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eik.h")
+
+eik = pytest.importorskip("paper_2106_15869_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eik_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(eik.LIB_PATH):
+        pytest.fail("libeik.so is not built (python -m paper_2106_15869_amd.build)")
+    return eik.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(eik.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version_and_status_strings(lib):
+    assert eik.eik_abi_version() == 1
+    assert eik.eik_status_string(0) == "EIK_OK"
+    assert eik.eik_status_string(2) == "EIK_ERR_NO_CONVERGENCE"
+    assert eik.eik_status_string(99) == "EIK_UNKNOWN_STATUS"
+
+
+def test_default_options(lib):
+    o = eik.EikOptions()
+    lib.eik_default_options(ctypes.byref(o))
+    assert o.dtype == eik.EIK_FLOAT32 and o.variant == eik.EIK_VARIANT_TILE
+    assert o.flags == 0 and o.max_iters == 0 and not o.workspace
+
+
+def test_options_struct_layout():
+    # mirrors eik_options in include/eik.h on LP64
+    assert ctypes.sizeof(eik.EikOptions) == 80
+    assert eik.EikOptions.max_iters.offset == 24
+    assert eik.EikOptions.stats.offset == 72
+    assert ctypes.sizeof(eik.EikStats) == 64
+
+
+def test_workspace_size(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    n = 64 * 64
+    ws = eik.eik_workspace_size((64, 64), o)
+    assert ws >= 13 * n  # labels + stamps + two lists
+    od = eik.make_options(eik.EIK_FLOAT64, "node", deterministic=True)
+    assert eik.eik_workspace_size((64, 64), od) >= ws + 8 * n
+    assert eik.eik_workspace_size((7, 9, 5), eik.make_options(eik.EIK_FLOAT32, "tile")) > 0
+    # invalid shapes give 0
+    assert eik.eik_workspace_size((0, 5), o) == 0
+    assert eik.eik_workspace_size((5,), o) == 0
+    assert eik.eik_workspace_size((2, 2, 2, 2), o) == 0
+    assert eik.eik_workspace_size((1 << 16, 1 << 16), o) == 0
+
+
+def _solve_raw(lib, dims, h=1.0, sources=(0,), eps=0.0, opt=None, F=0x1000, phi=0x2000):
+    d = np.asarray(dims, dtype=np.int64)
+    s = np.asarray(sources, dtype=np.int64)
+    return lib.eik_solve(F, len(d), d.ctypes.data, h, s.ctypes.data if s.size else None, len(s),
+                         eps, phi, ctypes.byref(opt) if opt is not None else None)
+
+
+@pytest.mark.parametrize("kwargs,why", [
+    (dict(dims=(4,)), "ndim"),
+    (dict(dims=(4, 0)), "dim"),
+    (dict(dims=(4, 4), h=0.0), "h"),
+    (dict(dims=(4, 4), h=float("nan")), "h"),
+    (dict(dims=(4, 4), h=float("inf")), "h"),
+    (dict(dims=(4, 4), eps=-1.0), "eps"),
+    (dict(dims=(4, 4), sources=()), "source"),
+    (dict(dims=(4, 4), sources=(16,)), "range"),
+    (dict(dims=(4, 4), sources=(-1,)), "range"),
+    (dict(dims=(4, 4), F=None), "NULL"),
+    (dict(dims=(4, 4), phi=None), "NULL"),
+    (dict(dims=(4, 4), phi=0x1000), "alias"),
+])
+def test_invalid_arguments_rejected_before_device_work(lib, kwargs, why):
+    rc = _solve_raw(lib, **kwargs)
+    assert rc == eik.EIK_ERR_INVALID_ARGUMENT
+    assert why.lower() in lib.eik_last_error().decode().lower()
+
+
+def test_invalid_options_rejected(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "tile", deterministic=True)
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    o.dtype = 7
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node", async_=True)  # no workspace
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    o.workspace = 0x1001  # misaligned
+    o.workspace_bytes = 1 << 20
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    o.workspace = 0x100000
+    o.workspace_bytes = 16  # too small
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_OUT_OF_MEMORY
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    o.flags = 64
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+
+
+def test_bad_source_values_rejected(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    vals = np.array([np.nan])
+    o.source_values = vals.ctypes.data
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+
+
+def test_apply_local_and_adjoint_validation(lib):
+    d = np.asarray((4, 4), dtype=np.int64)
+    assert lib.eik_apply_local(0x1000, 0x2000, 2, d.ctypes.data, 1.0, 0x2000, None) == \
+        eik.EIK_ERR_INVALID_ARGUMENT
+    assert lib.eik_apply_local(0x1000, 0x2000, 2, d.ctypes.data, -1.0, 0x3000, None) == \
+        eik.EIK_ERR_INVALID_ARGUMENT
+    s = np.asarray([99], dtype=np.int64)
+    assert lib.eik_adjoint(0x1000, 0x2000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0x3000, 0x4000,
+                           None) == eik.EIK_ERR_INVALID_ARGUMENT
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        eik.solve(torch.ones(4, 4), 1.0, [0])

@@ -1,0 +1,201 @@
+"""GPU parity of eik_solve / eik_apply_local against the oracle.
+
+Tolerances (max over finite nodes of |phi_gpu - phi_oracle|, relative to the
+largest finite arrival time): 1e-5 in float32, 1e-12 in float64; the +inf
+masks must be identical.  The oracle solves the same float32-rounded speed
+upcast to float64.  In the synchronous-read mode the node-list kernels must
+reproduce the serial Algorithm 2 emulation bit for bit, including its work
+counters, in the same precision."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+eik = pytest.importorskip("paper_2106_15869_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {np.float32: 1e-5, np.float64: 1e-12}
+VARIANTS = ["node", "tile"]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_solve(P, dtype, **kw):
+    F = dev(P.F.astype(dtype))
+    print(f"[case] {P.name} {np.dtype(dtype).name} {kw}", flush=True)
+    phi, st = eik.solve(F, P.h, P.sources, eps=P.eps, source_values=P.source_values, stats=True, **kw)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), st
+
+
+def ref_solve(P, dtype):
+    return oracle.fmm(P.F.astype(dtype).astype(np.float64), P.h, P.sources, values=P.source_values)
+
+
+def assert_close(got, ref, dtype):
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got)), "infinity masks differ"
+    if not fin.any():
+        return
+    err = float(np.max(np.abs(got[fin].astype(np.float64) - ref[fin])))
+    assert err <= TOL[dtype] * float(np.max(np.abs(ref[fin]))) + 1e-300, err
+
+
+def fuzz_cases():
+    out = []
+    for s in range(6):
+        out.append(W.random_problem(2000 + s, 2, 40, zero_frac=0.15 if s % 2 else 0.0))
+    for s in range(4):
+        out.append(W.random_problem(3000 + s, 3, 14, zero_frac=0.15 if s % 2 else 0.0))
+    return out
+
+
+def workload_cases():
+    return [
+        W.lognormal_2d(64),
+        W.lognormal_2d(300, seed=11),
+        W.Problem("maze2d_200", W.maze_field((200, 200), 3, free_coord=(0, 0)), 1.0, np.array([0])),
+        W.maze_3d(40),
+        W.layered_3d(33),
+    ]
+
+
+# ---------------------------------------------------------------------------
+# local solver
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape", [(37, 53), (9, 13, 17), (1, 70), (70, 1), (1, 1, 5)])
+def test_apply_local_bitwise(dtype, shape):
+    """One dense pass of the local solve equals the oracle's, bit for bit, on
+    values that exercise one-, two- and three-sided updates, +inf neighbours
+    and barriers."""
+    r = np.random.default_rng(sum(shape))
+    F = np.exp(r.uniform(-2, 2, size=shape))
+    F[r.random(shape) < 0.1] = 0.0
+    phi = r.uniform(0, 5, size=shape)
+    phi[r.random(shape) < 0.2] = np.inf
+    F, phi = F.astype(dtype), phi.astype(dtype)
+    got = eik.apply_local(dev(F), dev(phi), 0.7).cpu().numpy()
+    want = oracle.apply_local(F, 0.7, phi, dtype=dtype)
+    assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2, synchronous reads: bitwise against the serial emulation
+# ---------------------------------------------------------------------------
+STAT_KEYS = ("step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
+             "remedy_initial", "max_active")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("P", [W.tiny_constant()] + workload_cases()[:3] + fuzz_cases()[:6],
+                         ids=lambda P: P.name)
+def test_deterministic_matches_emulation(P, dtype):
+    got, st = gpu_solve(P, dtype, variant="node", deterministic=True)
+    want, wst = oracle.ifim(P.F.astype(dtype), P.h, P.sources, values=P.source_values, eps=P.eps,
+                            dtype=dtype)
+    assert np.array_equal(got, want)
+    for k in STAT_KEYS:
+        assert st[k] == wst[k], (k, st[k], wst[k])
+    got2, st2 = gpu_solve(P, dtype, variant="node", deterministic=True, skip_remedy=True)
+    want2, _ = oracle.ifim(P.F.astype(dtype), P.h, P.sources, values=P.source_values, eps=P.eps,
+                           dtype=dtype, skip_remedy=True)
+    assert np.array_equal(got2, want2)
+
+
+def test_update_step_alone_exact_for_single_constant_front():
+    """Example 1's observation on the GPU: no remedy needed for one front at
+    constant speed; the update step alone already gives the solution."""
+    P = W.tiny_constant()
+    ref = ref_solve(P, np.float64)
+    for variant in VARIANTS:
+        got, st = gpu_solve(P, np.float64, variant=variant, skip_remedy=True)
+        assert_close(got, ref, np.float64)
+        got, st = gpu_solve(P, np.float64, variant=variant)
+        assert st["remedy_initial"] == 0
+        assert_close(got, ref, np.float64)
+
+
+# ---------------------------------------------------------------------------
+# default (in-place) schedules against fast marching
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("P", fuzz_cases() + workload_cases(), ids=lambda P: P.name)
+def test_solve_matches_oracle(P, dtype, variant):
+    got, st = gpu_solve(P, dtype, variant=variant)
+    assert_close(got, ref_solve(P, dtype), dtype)
+
+
+def _edge_cases():
+    c = []
+    c.append(W.Problem("single_node", np.ones((1, 1)), 1.0, np.array([0])))
+    c.append(W.Problem("single_node_3d", np.ones((1, 1, 1)), 1.0, np.array([0])))
+    c.append(W.Problem("strip_x", np.linspace(0.5, 2, 97).reshape(1, 97), 0.3, np.array([40])))
+    c.append(W.Problem("strip_y", np.linspace(0.5, 2, 97).reshape(97, 1), 0.3, np.array([96])))
+    c.append(W.Problem("strip_z", np.linspace(0.5, 2, 45).reshape(45, 1, 1), 0.3, np.array([0])))
+    Fb = np.zeros((20, 30))
+    Fb[0, 0] = 1.0
+    c.append(W.Problem("all_barrier", Fb, 1.0, np.array([0])))
+    Fw = np.ones((40, 40))
+    Fw[:, 20] = 0.0
+    c.append(W.Problem("wall_unreachable", Fw, 1.0, np.array([5])))
+    Fz = np.ones((16, 16))
+    Fz[3, 3] = 0.0
+    c.append(W.Problem("source_on_barrier", Fz, 1.0, np.array([3 * 16 + 3])))
+    c.append(W.Problem("corners_with_values", np.ones((33, 47)), 0.5,
+                       np.array([0, 46, 32 * 47, 33 * 47 - 1, 46]),
+                       source_values=np.array([0.0, 2.0, 1.0, 3.5, 0.25])))
+    c.append(W.Problem("all_sources", np.ones((5, 6)), 1.0, np.arange(30)))
+    c.append(W.Problem("ragged_3d", np.exp(np.random.default_rng(1).uniform(-1, 1, (13, 7, 29))),
+                       1.3, np.array([100, 2000])))
+    return c
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("P", _edge_cases(), ids=lambda P: P.name)
+def test_edge_cases(P, dtype, variant):
+    got, _ = gpu_solve(P, dtype, variant=variant)
+    assert_close(got, ref_solve(P, dtype), dtype)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_invalid_speed_reported(variant):
+    F = np.ones((16, 16), dtype=np.float32)
+    F[3, 4] = -1.0
+    with pytest.raises(eik.EikError) as e:
+        eik.solve(dev(F), 1.0, [0], variant=variant)
+    assert e.value.status == eik.EIK_ERR_INVALID_ARGUMENT
+    F[3, 4] = np.nan
+    with pytest.raises(eik.EikError):
+        eik.solve(dev(F), 1.0, [0], variant=variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_iteration_cap_reported(variant):
+    P = W.lognormal_2d(64)
+    with pytest.raises(eik.EikError) as e:
+        eik.solve(dev(P.F), P.h, P.sources, variant=variant, max_iters=2)
+    assert e.value.status == eik.EIK_ERR_NO_CONVERGENCE
+
+
+def test_workspace_reuse_and_streams():
+    """Two solves sharing one workspace on a side stream give the same result
+    as fresh ones."""
+    P1, P2 = W.lognormal_2d(128, seed=3), W.lognormal_2d(128, seed=4)
+    ws_bytes = eik.eik_workspace_size(P1.dims, eik.make_options(eik.EIK_FLOAT32, "tile"))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = eik.solve(dev(P1.F), P1.h, P1.sources, workspace=ws)
+        b = eik.solve(dev(P2.F), P2.h, P2.sources, workspace=ws)
+    s.synchronize()
+    assert_close(a.cpu().numpy(), ref_solve(P1, np.float32), np.float32)
+    assert_close(b.cpu().numpy(), ref_solve(P2, np.float32), np.float32)
