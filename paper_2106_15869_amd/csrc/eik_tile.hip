@@ -1,15 +1,669 @@
+// Tile-activated IFIM for gfx950.
+//
+// The grid is cut into tiles of TZ x TY x TX nodes.  A launch processes a list
+// of tiles, one workgroup (256 lanes, four wave64) per tile at a time.  Each
+// workgroup stages the tile's values and labels plus a one-cell halo in LDS,
+// then runs the node rules of Algorithm 2 for several inner iterations
+// without touching HBM, and writes back what changed.
+//
+//   update step (STEP 2): FAR nodes with F > 0 next to a converged or fixed
+//     node become active; active nodes take phi~ = G_i(phi); a node whose
+//     value no longer moves (phi - phi~ <= eps) converges and activates its FAR
+//     neighbours -- no convergence check of those neighbours (Section 3.3).
+//     A node converging on a tile face schedules the tile across that face; a
+//     tile that still holds active nodes schedules itself.
+//   remedy detection (STEP 3, first part): one dense pass over all tiles;
+//     a tile with any node whose phi~ < phi - eps enters the remedy list.
+//   remedy loop (STEP 3): every non-source node of a listed tile is
+//     recomputed until nothing in the tile changes (the remedy loop restricted
+//     to the tile); a change on a tile face schedules the tile across it.
+// Within an inner iteration all phi~ are computed before any is applied (two
+// LDS phases), so a tile's iterations are synchronous; tiles of one launch see
+// each other's values only through the halo staged at the start.
+#include <utility>
+#include <vector>
+
+#include "eik_device.hpp"
 #include "eik_host.hpp"
 #include "eik_tile.hpp"
 
 namespace eik {
 
-size_t tile_workspace_bytes(const GridDims& g, const eik_options& o) { return 256; }
+namespace {
+
+// LDS label byte: bits 0-1 state, bit 2 passable (F > 0), bit 3 outside grid.
+constexpr uint8_t kPass = 4u, kOut = 8u;
+
+struct TileGeom {
+    int nx, ny, nz;   // grid
+    int ntx, nty, ntz;
+    int ntiles;
+};
 
 template <typename T>
-eik_status solve_tile(const GridDims& g, const T* F, double h, double eps,
-                      const std::vector<std::pair<int, double>>& src, T* phi,
-                      const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
-    return fail(EIK_ERR_UNSUPPORTED, "tile variant not built yet");
+struct TileIter {
+    const T* F;
+    T* phi;
+    uint8_t* lab;
+    uint32_t* tstamp;
+    const int* list_cur;
+    int* list_next;
+    int* cnt_cur;
+    int* cnt_next;
+    int* cnt_zero;
+    Ctl* ctl;
+    int tag_slot;
+    int phase;  // 0 update step, 1 remedy loop
+    int first;  // first launch of the remedy loop
+};
+
+__device__ __forceinline__ bool claim_tile(uint32_t* tstamp, int t, uint32_t tag) {
+    if (__hip_atomic_load(tstamp + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tag) return false;
+    return atomicMax(tstamp + t, tag) < tag;
+}
+
+__device__ __forceinline__ void push_tile(uint32_t* tstamp, int t, uint32_t tag, int* list, int* cnt) {
+    if (claim_tile(tstamp, t, tag)) list[atomicAdd(cnt, 1)] = t;
+}
+
+template <int ND, int TX, int TY, int TZ>
+struct Shape {
+    static constexpr int LX = TX + 2;
+    static constexpr int LY = TY + 2;
+    static constexpr int LZ = ND == 3 ? TZ + 2 : 1;
+    static constexpr int NT = TX * TY * (ND == 3 ? TZ : 1);
+    static constexpr int NL = LX * LY * LZ;
+    static constexpr int NPT = (NT + kBlock - 1) / kBlock;
+    static constexpr int SY = LX;
+    static constexpr int SZ = LX * LY;
+};
+
+// Per-lane description of the nodes a lane owns in the current tile.
+template <typename T, int NPT>
+struct Owned {
+    int G[NPT];      // global index
+    int L[NPT];      // LDS index (with halo)
+    int face[NPT];   // bit d set: node on the tile face in direction d (-x,+x,-y,+y,-z,+z)
+                     // and the grid continues across it
+    T H[NPT];
+    bool ok[NPT];
+};
+
+// Stage the tile and its halo: values (+inf outside) and labels (kOut outside).
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void stage(const TileGeom& g, int x0, int y0, int z0, const T* phi,
+                                      const uint8_t* lab, T* sphi, uint8_t* sl) {
+    using S = Shape<ND, TX, TY, TZ>;
+    const T inf = pos_inf<T>();
+    for (int q = threadIdx.x; q < S::NL; q += kBlock) {
+        const int lx = q % S::LX;
+        const int ly = (q / S::LX) % S::LY;
+        const int lz = q / (S::LX * S::LY);
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
+        const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+        if (in) {
+            const int G = (gz * g.ny + gy) * g.nx + gx;
+            sphi[q] = phi[G];
+            sl[q] = lab[G];
+        } else {
+            sphi[q] = inf;
+            sl[q] = kOut;
+        }
+    }
+}
+
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void own_nodes(const TileGeom& g, int x0, int y0, int z0, const T* F, T h,
+                                          Owned<T, Shape<ND, TX, TY, TZ>::NPT>& o) {
+    using S = Shape<ND, TX, TY, TZ>;
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        const int n = threadIdx.x + r * kBlock;
+        const int x = n % TX, y = (n / TX) % TY, z = ND == 3 ? n / (TX * TY) : 0;
+        const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
+        o.ok[r] = n < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
+        o.G[r] = (gz * g.ny + gy) * g.nx + gx;
+        o.L[r] = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
+        int f = 0;
+        if (x == 0 && gx > 0) f |= 1;
+        if (x == TX - 1 && gx + 1 < g.nx) f |= 2;
+        if (y == 0 && gy > 0) f |= 4;
+        if (y == TY - 1 && gy + 1 < g.ny) f |= 8;
+        if (ND == 3) {
+            if (z == 0 && gz > 0) f |= 16;
+            if (z == TZ - 1 && gz + 1 < g.nz) f |= 32;
+        }
+        o.face[r] = f;
+        o.H[r] = pos_inf<T>();
+        if (o.ok[r]) o.H[r] = cell_H(h, F[o.G[r]]);
+    }
+}
+
+// G_i from the LDS tile (halo holds +inf outside the grid).
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ T eval_lds(const T* sphi, int L, T H) {
+    using S = Shape<ND, TX, TY, TZ>;
+    const T ax = tmin(sphi[L - 1], sphi[L + 1]);
+    const T ay = tmin(sphi[L - S::SY], sphi[L + S::SY]);
+    if (ND == 2) return godunov<T, 2>(ay, ax, pos_inf<T>(), H);
+    const T az = tmin(sphi[L - S::SZ], sphi[L + S::SZ]);
+    return godunov<T, 3>(az, ay, ax, H);
+}
+
+template <int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ int lds_offset(int d) {
+    using S = Shape<ND, TX, TY, TZ>;
+    switch (d) {
+        case 0: return -1;
+        case 1: return 1;
+        case 2: return -S::SY;
+        case 3: return S::SY;
+        case 4: return -S::SZ;
+        default: return S::SZ;
+    }
+}
+
+__device__ __forceinline__ int neighbour_tile(const TileGeom& g, int t, int d) {
+    switch (d) {
+        case 0: return t - 1;
+        case 1: return t + 1;
+        case 2: return t - g.ntx;
+        case 3: return t + g.ntx;
+        case 4: return t - g.ntx * g.nty;
+        default: return t + g.ntx * g.nty;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t launch_prologue(const TileIter<T>& a, int n) {
+    const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *a.cnt_zero = 0;
+        a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
+        if (n > 0) {
+            if (a.phase == 0) {
+                a.ctl->iters2 += 1;
+                if (static_cast<unsigned long long>(n) > a.ctl->max_active)
+                    a.ctl->max_active = static_cast<unsigned long long>(n);
+            } else {
+                a.ctl->iters3 += 1;
+            }
+        }
+        if (a.first) a.ctl->remedy_init = static_cast<unsigned long long>(n);
+    }
+    return tag + 1;  // claims made by this launch build the next list
+}
+
+// ---------------------------------------------------------------------------
+// STEP 2 on tiles
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom g, T h, T eps,
+                                                        int inner) {
+    using S = Shape<ND, TX, TY, TZ>;
+    __shared__ T sphi[S::NL];
+    __shared__ uint8_t sl[S::NL];
+    __shared__ int s_face;
+    __shared__ int s_evals;
+    const T inf = pos_inf<T>();
+    const int n = *a.cnt_cur;
+    const uint32_t ntag = launch_prologue(a, n);
+    unsigned long long evals = 0;
+    for (int e = blockIdx.x; e < n; e += gridDim.x) {
+        const int t = a.list_cur[e];
+        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        Owned<T, S::NPT> o;
+        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        if (threadIdx.x == 0) {
+            s_face = 0;
+            s_evals = 0;
+        }
+        __syncthreads();
+        uint8_t lab0[S::NPT];
+        T phi0[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            lab0[r] = o.ok[r] ? sl[o.L[r]] : uint8_t(0);
+            phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
+            if (o.ok[r] && o.H[r] < inf) sl[o.L[r]] = lab0[r] | kPass;
+        }
+        __syncthreads();
+        // FAR nodes next to a converged / fixed node join the active set
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            if (!o.ok[r]) continue;
+            const uint8_t me = sl[o.L[r]];
+            if ((me & 3u) != L_FAR || !(me & kPass)) continue;
+            bool act = false;
+#pragma unroll
+            for (int d = 0; d < 2 * ND; ++d) {
+                const uint8_t nb = sl[o.L[r] + lds_offset<ND, TX, TY, TZ>(d)];
+                const uint32_t st = nb & 3u;
+                act |= !(nb & kOut) && (st == L_CONV || st == L_FIXED);
+            }
+            if (act) sl[o.L[r]] = (me & ~3u) | L_ACTIVE;
+        }
+        __syncthreads();
+        bool any_active = false;
+        int my_evals = 0;
+        for (int it = 0;; ++it) {
+            T pt[S::NPT];
+            bool act[S::NPT];
+            bool has = false;
+#pragma unroll
+            for (int r = 0; r < S::NPT; ++r) {
+                act[r] = o.ok[r] && (sl[o.L[r]] & 3u) == L_ACTIVE;
+                pt[r] = inf;
+                if (act[r]) {
+                    pt[r] = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
+                    has = true;
+                }
+            }
+            any_active = __syncthreads_or(has);
+            if (!any_active || it == inner) break;
+#pragma unroll
+            for (int r = 0; r < S::NPT; ++r) {
+                if (!act[r]) continue;
+                ++my_evals;
+                const int L = o.L[r];
+                const T cur = sphi[L];
+                if (pt[r] < inf && cur - pt[r] <= eps) {
+                    sl[L] = (sl[L] & ~3u) | L_CONV;
+                    int fm = 0;
+#pragma unroll
+                    for (int d = 0; d < 2 * ND; ++d) {
+                        const int q = L + lds_offset<ND, TX, TY, TZ>(d);
+                        const uint8_t nb = sl[q];
+                        if (o.face[r] & (1 << d)) {
+                            if ((nb & 3u) == L_FAR) fm |= 1 << d;  // neighbour tile must look
+                        } else if (!(nb & kOut) && (nb & 3u) == L_FAR && (nb & kPass)) {
+                            sl[q] = (nb & ~3u) | L_ACTIVE;
+                        }
+                    }
+                    if (fm) atomicOr(&s_face, fm);
+                } else if (!(pt[r] < inf)) {
+                    sl[L] = (sl[L] & ~3u) | L_FAR;
+                } else if (pt[r] < cur) {
+                    sphi[L] = pt[r];
+                }
+            }
+            __syncthreads();
+        }
+        // write back what changed
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            if (!o.ok[r]) continue;
+            const uint8_t st = sl[o.L[r]] & 3u;
+            if (st != (lab0[r] & 3u)) a.lab[o.G[r]] = st;
+            const T v = sphi[o.L[r]];
+            if (v != phi0[r]) a.phi[o.G[r]] = v;
+        }
+        if (my_evals) atomicAdd(&s_evals, my_evals);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (any_active) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+            const int fm = s_face;
+            for (int d = 0; d < 2 * ND; ++d)
+                if (fm & (1 << d)) push_tile(a.tstamp, neighbour_tile(g, t, d), ntag, a.list_next, a.cnt_next);
+            evals += static_cast<unsigned long long>(s_evals);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals2, evals);
+}
+
+// ---------------------------------------------------------------------------
+// STEP 3: whole-grid detection, one workgroup per tile
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom g, T h, T eps) {
+    using S = Shape<ND, TX, TY, TZ>;
+    __shared__ T sphi[S::NL];
+    __shared__ uint8_t sl[S::NL];
+    const uint32_t ntag = launch_prologue(a, 0);
+    const int t = blockIdx.x;
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+    stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+    Owned<T, S::NPT> o;
+    own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+    __syncthreads();
+    bool flag = false;
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
+        const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
+        flag |= pt < sphi[o.L[r]] - eps;
+    }
+    if (__syncthreads_or(flag) && threadIdx.x == 0) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+}
+
+// ---------------------------------------------------------------------------
+// STEP 3: remedy loop on tiles
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom g, T h, T eps,
+                                                        int inner) {
+    using S = Shape<ND, TX, TY, TZ>;
+    __shared__ T sphi[S::NL];
+    __shared__ uint8_t sl[S::NL];
+    __shared__ int s_face;
+    __shared__ int s_evals;
+    const T inf = pos_inf<T>();
+    const int n = *a.cnt_cur;
+    const uint32_t ntag = launch_prologue(a, n);
+    unsigned long long evals = 0;
+    for (int e = blockIdx.x; e < n; e += gridDim.x) {
+        const int t = a.list_cur[e];
+        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        Owned<T, S::NPT> o;
+        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        if (threadIdx.x == 0) {
+            s_face = 0;
+            s_evals = 0;
+        }
+        __syncthreads();
+        bool live[S::NPT];
+        T phi0[S::NPT];
+        int nlive = 0;
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            live[r] = o.ok[r] && (sl[o.L[r]] & 3u) != L_FIXED;
+            phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
+            nlive += live[r] ? 1 : 0;
+        }
+        bool pending = false;
+        int my_evals = 0;
+        for (int it = 0;; ++it) {
+            T pt[S::NPT];
+            bool ch[S::NPT];
+            bool has = false;
+#pragma unroll
+            for (int r = 0; r < S::NPT; ++r) {
+                ch[r] = false;
+                pt[r] = inf;
+                if (live[r]) {
+                    pt[r] = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
+                    ch[r] = pt[r] < sphi[o.L[r]] - eps;
+                    has |= ch[r];
+                }
+            }
+            my_evals += nlive;
+            pending = __syncthreads_or(has);
+            if (!pending || it == inner) break;
+            int fm = 0;
+#pragma unroll
+            for (int r = 0; r < S::NPT; ++r) {
+                if (!ch[r]) continue;
+                sphi[o.L[r]] = pt[r];
+                fm |= o.face[r];
+            }
+            if (fm) atomicOr(&s_face, fm);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            if (!o.ok[r]) continue;
+            const T v = sphi[o.L[r]];
+            if (v != phi0[r]) a.phi[o.G[r]] = v;
+        }
+        if (my_evals) atomicAdd(&s_evals, my_evals);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (pending) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+            const int fm = s_face;
+            for (int d = 0; d < 2 * ND; ++d)
+                if (fm & (1 << d)) push_tile(a.tstamp, neighbour_tile(g, t, d), ntag, a.list_next, a.cnt_next);
+            evals += static_cast<unsigned long long>(s_evals);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals_rem, evals);
+}
+
+// ---------------------------------------------------------------------------
+// STEP 1 helpers
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
+}
+
+// Initial tile list: tiles holding a grid neighbour of a source (claimed with tag 1).
+template <typename T>
+__global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcBatch<T> b,
+                             uint32_t* tstamp, int* list, int* cnt) {
+    const int k = threadIdx.x;
+    if (k >= b.count) return;
+    const int i = b.idx[k];
+    const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
+    const int dx[6] = {-1, 1, 0, 0, 0, 0}, dy[6] = {0, 0, -1, 1, 0, 0}, dz[6] = {0, 0, 0, 0, -1, 1};
+    for (int d = 0; d < 2 * nd; ++d) {
+        const int X = x + dx[d], Y = y + dy[d], Z = z + dz[d];
+        if (X < 0 || X >= g.nx || Y < 0 || Y >= g.ny || Z < 0 || Z >= g.nz) continue;
+        const int t = ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_);
+        push_tile(tstamp, t, 1u, list, cnt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct TileCfg {
+    int tx, ty, tz;
+};
+
+TileCfg pick_tile(const GridDims& gd, const eik_options& o) {
+    TileCfg c{o.tile[2], o.tile[1], o.tile[0]};
+    if (gd.nd == 2) {
+        c.tz = 1;
+        if (c.tx == 0 || c.ty == 0) c = TileCfg{32, 32, 1};
+    } else if (c.tx == 0 || c.ty == 0 || c.tz == 0) {
+        c = TileCfg{8, 8, 8};
+    }
+    return c;
+}
+
+TileGeom make_geom(const GridDims& gd, const TileCfg& c) {
+    TileGeom g;
+    g.nx = gd.nx;
+    g.ny = gd.ny;
+    g.nz = gd.nz;
+    g.ntx = (gd.nx + c.tx - 1) / c.tx;
+    g.nty = (gd.ny + c.ty - 1) / c.ty;
+    g.ntz = (gd.nz + c.tz - 1) / c.tz;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+    return g;
+}
+
+struct TileWs {
+    Ctl* ctl;
+    uint8_t* lab;
+    uint32_t* tstamp;
+    int* list[2];
+    size_t bytes;
+};
+
+TileWs tile_layout(char* base, int64_t n, int ntiles) {
+    TileWs w{};
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + b, 256);
+        return p;
+    };
+    w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
+    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
+    w.list[0] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
+    w.list[1] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
+    w.bytes = off;
+    return w;
+}
+
+template <typename T, int ND, int TX, int TY, int TZ>
+struct TileKernels {
+    static hipError_t update(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner, int blocks,
+                             hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(blocks), dim3(kBlock), 0, s, a, g, h,
+                           eps, inner);
+        return hipGetLastError();
+    }
+    static hipError_t detect(const TileIter<T>& a, const TileGeom& g, T h, T eps, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(g.ntiles), dim3(kBlock), 0, s, a, g, h,
+                           eps);
+        return hipGetLastError();
+    }
+    static hipError_t remedy(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner, int blocks,
+                             hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(blocks), dim3(kBlock), 0, s, a, g, h,
+                           eps, inner);
+        return hipGetLastError();
+    }
+};
+
+template <typename T>
+struct TileOps {
+    hipError_t (*update)(const TileIter<T>&, const TileGeom&, T, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*detect)(const TileIter<T>&, const TileGeom&, T, T, hipStream_t) = nullptr;
+    hipError_t (*remedy)(const TileIter<T>&, const TileGeom&, T, T, int, int, hipStream_t) = nullptr;
+};
+
+template <typename T, int ND, int TX, int TY, int TZ>
+TileOps<T> ops_of() {
+    TileOps<T> k;
+    k.update = &TileKernels<T, ND, TX, TY, TZ>::update;
+    k.detect = &TileKernels<T, ND, TX, TY, TZ>::detect;
+    k.remedy = &TileKernels<T, ND, TX, TY, TZ>::remedy;
+    return k;
+}
+
+// Supported tile shapes (z, y, x).
+template <typename T>
+bool select_ops(int nd, const TileCfg& c, TileOps<T>& k) {
+    if (nd == 2) {
+        if (c.ty == 16 && c.tx == 16) return k = ops_of<T, 2, 16, 16, 1>(), true;
+        if (c.ty == 32 && c.tx == 32) return k = ops_of<T, 2, 32, 32, 1>(), true;
+        if (c.ty == 16 && c.tx == 64) return k = ops_of<T, 2, 64, 16, 1>(), true;
+        if (c.ty == 8 && c.tx == 32) return k = ops_of<T, 2, 32, 8, 1>(), true;
+        if (c.ty == 64 && c.tx == 64) return k = ops_of<T, 2, 64, 64, 1>(), true;
+        return false;
+    }
+    if (c.tz == 8 && c.ty == 8 && c.tx == 8) return k = ops_of<T, 3, 8, 8, 8>(), true;
+    if (c.tz == 4 && c.ty == 8 && c.tx == 8) return k = ops_of<T, 3, 8, 8, 4>(), true;
+    if (c.tz == 4 && c.ty == 4 && c.tx == 16) return k = ops_of<T, 3, 16, 4, 4>(), true;
+    if (c.tz == 8 && c.ty == 8 && c.tx == 16) return k = ops_of<T, 3, 16, 8, 8>(), true;
+    if (c.tz == 16 && c.ty == 16 && c.tx == 16) return k = ops_of<T, 3, 16, 16, 16>(), true;
+    return false;
+}
+
+}  // namespace
+
+size_t tile_workspace_bytes(const GridDims& gd, const eik_options& o) {
+    TileCfg c = pick_tile(gd, o);
+    TileGeom g = make_geom(gd, c);
+    return tile_layout(nullptr, gd.n, g.ntiles).bytes;
+}
+
+template <typename T>
+eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
+                      const std::vector<std::pair<int, double>>& src, T* phi, const eik_options& o,
+                      char* ws, hipStream_t s, eik_stats* st) {
+    const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
+    TileCfg c = pick_tile(gd, o);
+    TileOps<T> k;
+    if (!select_ops<T>(gd.nd, c, k)) return fail(EIK_ERR_INVALID_ARGUMENT, "unsupported tile shape");
+    TileGeom g = make_geom(gd, c);
+    TileWs w = tile_layout(ws, gd.n, g.ntiles);
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * static_cast<int64_t>(gd.n) + 64;
+    const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
+    const int blocks = std::min(g.ntiles, 2048);
+    int64_t launched = 0;
+
+    HIP_TRY(launch_ctl_init(w.ctl, s));
+    HIP_TRY(launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s));
+    hipLaunchKernelGGL(k_zero_u32, dim3(std::min((g.ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
+                       w.tstamp, g.ntiles);
+    HIP_TRY(hipGetLastError());
+    launched += 3;
+    std::vector<SrcBatch<T>> batches;
+    for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
+        SrcBatch<T> b{};
+        b.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, src.size() - q));
+        for (int j = 0; j < b.count; ++j) {
+            b.idx[j] = src[q + j].first;
+            b.val[j] = static_cast<T>(src[q + j].second);
+        }
+        batches.push_back(b);
+    }
+    for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
+    for (auto& b : batches) {
+        hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz, b,
+                           w.tstamp, w.list[0], &w.ctl->cnt[0]);
+        HIP_TRY(hipGetLastError());
+    }
+    launched += 2 * static_cast<int64_t>(batches.size());
+
+    const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
+    int64_t gl = 0;  // launches in the tag chain so far (selects the tag slot)
+    auto iter_args = [&](int64_t t, int phase) {
+        TileIter<T> a{};
+        a.F = F;
+        a.phi = phi;
+        a.lab = w.lab;
+        a.tstamp = w.tstamp;
+        a.list_cur = w.list[t & 1];
+        a.list_next = w.list[(t + 1) & 1];
+        a.cnt_cur = &w.ctl->cnt[t % 3];
+        a.cnt_next = &w.ctl->cnt[(t + 1) % 3];
+        a.cnt_zero = &w.ctl->cnt[(t + 2) % 3];
+        a.ctl = w.ctl;
+        a.tag_slot = static_cast<int>((gl + t) & 1);
+        a.phase = phase;
+        a.first = (phase == 1 && t == 0) ? 1 : 0;
+        return a;
+    };
+    auto counter = [&](int64_t t) { return &w.ctl->cnt[t % 3]; };
+
+    int64_t n2 = 0;
+    eik_status rc = run_loop([&](int64_t t) { return k.update(iter_args(t, 0), g, hT, eT, inner, blocks, s); },
+                             counter, cap, async, s, &n2);
+    gl += n2;
+    launched += n2;
+    if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
+        HIP_TRY(launch_reset_counters(w.ctl, s));
+        // detection appends into list 0 through counter 0 (t = -1 -> next = 0)
+        TileIter<T> d = iter_args(0, 1);
+        d.list_next = w.list[0];
+        d.cnt_next = &w.ctl->cnt[0];
+        d.cnt_zero = &w.ctl->cnt[2];
+        HIP_TRY(k.detect(d, g, hT, eT, s));
+        gl += 1;
+        launched += 2;
+        int64_t n3 = 0;
+        rc = run_loop([&](int64_t t) { return k.remedy(iter_args(t, 1), g, hT, eT, inner, blocks, s); },
+                      counter, cap, async, s, &n3);
+        launched += n3;
+    }
+    if (async) return rc;
+    HostSlots& hs = host_slots();
+    HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
+    if (st) {
+        st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
+        st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
+        st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
+        st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : gd.n - static_cast<int64_t>(src.size());
+        st->evals_remedy = static_cast<int64_t>(hs.ctl->evals_rem);
+        st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
+        st->max_active = static_cast<int64_t>(hs.ctl->max_active);
+        st->launches = launched;
+    }
+    return rc;
 }
 
 template eik_status solve_tile<float>(const GridDims&, const float*, double, double,
@@ -18,4 +672,5 @@ template eik_status solve_tile<float>(const GridDims&, const float*, double, dou
 template eik_status solve_tile<double>(const GridDims&, const double*, double, double,
                                        const std::vector<std::pair<int, double>>&, double*,
                                        const eik_options&, char*, hipStream_t, eik_stats*);
+
 }  // namespace eik
