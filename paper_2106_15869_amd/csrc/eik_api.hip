@@ -88,10 +88,17 @@ struct NodeWs {
     Ctl* ctl;
     uint8_t* lab;
     uint32_t* stamp;
-    int* list[2];
+    SegList seg[2];
     void* vals;
     size_t bytes;
 };
+
+// A segment holds what one workgroup can append from its slice of at most
+// ceil(N / G) entries, each producing at most 7 items (itself and 6
+// neighbours), plus room for source seeding.
+static int node_seg_cap(int64_t n) {
+    return static_cast<int>(7 * ((n + kNodeSegs - 1) / kNodeSegs) + 512);
+}
 
 static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
     NodeWs w{};
@@ -101,11 +108,15 @@ static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
         off = align_up(off + b, 256);
         return p;
     };
+    const int cap = node_seg_cap(n);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.stamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(n)));
-    w.list[0] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(n)));
-    w.list[1] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(n)));
+    for (int k = 0; k < 2; ++k) {
+        w.seg[k].cap = cap;
+        w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(kNodeSegs)));
+        w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * kNodeSegs));
+    }
     w.vals = det ? take(esz * static_cast<size_t>(n)) : nullptr;
     w.bytes = off;
     return w;
@@ -151,8 +162,6 @@ eik_status check_sources(const Problem& P, const int64_t* sources, int64_t n_sou
     return EIK_OK;
 }
 
-static int list_blocks() { return 512; }
-
 template <typename T>
 static eik_status solve_nodelist(const Problem& P, const T* F, double h, double eps,
                                  const std::vector<std::pair<int, double>>& src, T* phi,
@@ -178,9 +187,11 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         batches.push_back(b);
     }
     for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
-    for (auto& b : batches)
-        HIP_TRY(launch_seed_active<T>(P.g, F, w.lab, b, w.list[0], &w.ctl->cnt[0], s));
-    launched += 2 * static_cast<int64_t>(batches.size());
+    HIP_TRY(launch_seg_clear(w.seg[0].count, kNodeSegs, s));
+    for (size_t j = 0; j < batches.size(); ++j)
+        HIP_TRY(launch_seed_active<T>(P.g, F, w.lab, batches[j], w.seg[0],
+                                      static_cast<int>(j % kNodeSegs), s));
+    launched += 1 + 2 * static_cast<int64_t>(batches.size());
 
     const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
     auto iter_args = [&](int64_t t, bool first) {
@@ -190,31 +201,31 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         a.lab = w.lab;
         a.stamp = w.stamp;
         a.vals = static_cast<T*>(w.vals);
-        a.list_cur = w.list[t & 1];
-        a.list_next = w.list[(t + 1) & 1];
-        a.cnt_cur = &w.ctl->cnt[t % 3];
-        a.cnt_next = &w.ctl->cnt[(t + 1) % 3];
-        a.cnt_zero = &w.ctl->cnt[(t + 2) % 3];
+        a.cur = w.seg[t & 1];
+        a.next = w.seg[(t + 1) & 1];
         a.ctl = w.ctl;
         a.tag_slot = static_cast<int>(t & 1);
         a.first = first ? 1 : 0;
         return a;
     };
-    auto counter = [&](int64_t t) { return &w.ctl->cnt[t % 3]; };
+    auto counts = [&](int64_t t) { return w.seg[t & 1].count; };
+    const int per_iter = det ? 2 : 1;
 
     // STEP 2
+    int64_t n2 = 0, n3 = 0;
     eik_status rc = run_loop(
-        [&](int64_t t) { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, list_blocks(), s); },
-        counter, cap, async, s, &launched);
+        [&](int64_t t) { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); },
+        counts, kNodeSegs, cap, async, s, &n2);
+    launched += per_iter * n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
-        // STEP 3a: whole-grid check
-        HIP_TRY(launch_reset_counters(w.ctl, s));
-        HIP_TRY(launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.list[0], &w.ctl->cnt[0], s));
-        launched += 2;
+        // STEP 3a: whole-grid check into list 0
+        HIP_TRY(launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.seg[0], s));
+        launched += 1;
         // STEP 3b: remedy loop
         rc = run_loop(
-            [&](int64_t t) { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, list_blocks(), s); },
-            counter, cap, async, s, &launched);
+            [&](int64_t t) { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); },
+            counts, kNodeSegs, cap, async, s, &n3);
+        launched += per_iter * n3;
     }
     if (async) return rc;
     HostSlots& hs = host_slots();

@@ -12,7 +12,7 @@ struct Grid;
 
 // Device control block (lives in the workspace).
 struct Ctl {
-    int cnt[4];       // rotating list counters: iteration t reads cnt[t%3]
+    int cnt[4];       // spare counters
     int err;          // bit 0: F negative or not finite
     int tag[2];       // remedy stamp tags, alternating by iteration parity
     int pad;
@@ -29,8 +29,18 @@ struct SrcBatch {
     T val[kMaxSrcBatch];
 };
 
-// Pointers a node-list iteration needs; the driver rotates lists and
-// counters by iteration parity: list t&1 -> (t+1)&1, cnt t%3 -> (t+1)%3.
+// Segmented list (see eik_seglist.hpp): G regions of cap entries + G lengths.
+struct SegList {
+    int* data;
+    int* count;
+    int cap;
+};
+
+// Workgroups per list launch of the node-list variant (one segment each).
+constexpr int kNodeSegs = 512;
+
+// Pointers a node-list iteration needs; the driver alternates the two lists
+// by iteration parity.
 template <typename T>
 struct NodeIter {
     const T* F;
@@ -38,11 +48,8 @@ struct NodeIter {
     uint8_t* lab;
     uint32_t* stamp;
     T* vals;           // per-entry values (synchronous-read mode)
-    const int* list_cur;
-    int* list_next;
-    int* cnt_cur;
-    int* cnt_next;
-    int* cnt_zero;
+    SegList cur;
+    SegList next;
     Ctl* ctl;
     int tag_slot;      // parity of this iteration (remedy stamp tag slot)
     int first;         // first iteration of its loop
@@ -62,16 +69,15 @@ template <typename T>
 hipError_t launch_seed(T* phi, uint8_t* lab, const SrcBatch<T>& b, hipStream_t s);
 template <typename T>
 hipError_t launch_seed_active(const GridDims& g, const T* F, uint8_t* lab, const SrcBatch<T>& b,
-                              int* list, int* cnt, hipStream_t s);
+                              const SegList& out, int seg, hipStream_t s);
 template <typename T>
-hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
-                        int grid_blocks, hipStream_t s);
+hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
 template <typename T>
 hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, T h, T eps,
-                         int* list, int* cnt, hipStream_t s);
+                         const SegList& out, hipStream_t s);
 template <typename T>
-hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
-                         int grid_blocks, hipStream_t s);
+hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
+hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s);
 template <typename T>
 hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
                               hipStream_t s);

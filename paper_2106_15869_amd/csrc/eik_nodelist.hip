@@ -12,10 +12,12 @@
 //           drop form the Remedy list; k_remedy (or eval + apply): changed
 //           nodes take the new value and, with their neighbours, form the
 //           next Remedy list.
-// Lists are int32 node indices compacted per wave (prefix sum over lanes, one
-// atomic per wave).  Labels are bytes changed with word atomics.
+// Lists are int32 node indices in per-workgroup segments (eik_seglist.hpp):
+// each wave compacts its items with a lane prefix sum and reserves room with
+// one LDS atomic.  Labels are bytes changed with word atomics.
 #include "eik_device.hpp"
 #include "eik_internal.hpp"
+#include "eik_seglist.hpp"
 
 namespace eik {
 
@@ -27,24 +29,6 @@ static __host__ __device__ inline Grid make_grid(const GridDims& d) {
     g.n = d.n;
     g.sxy = d.nx * d.ny;
     return g;
-}
-
-// Append the set bits of `mask` (slots into items[]) to list, one atomic per wave.
-template <int MAXC>
-__device__ __forceinline__ void wave_append_mask(int* list, int* cnt, const int (&items)[MAXC],
-                                                 uint32_t mask) {
-    const int c = __popc(mask);
-    int incl = wave_incl_scan(c);
-    int total = __shfl(incl, 63, 64);
-    if (total == 0) return;
-    int base = 0;
-    if (lane_id() == 63) base = atomicAdd(cnt, total);
-    base = __shfl(base, 63, 64);
-    int pos = base + incl - c;
-#pragma unroll
-    for (int j = 0; j < MAXC; ++j) {
-        if (mask & (1u << j)) list[pos + __popc(mask & ((1u << j) - 1u))] = items[j];
-    }
 }
 
 // Neighbour slots in a fixed order: -x, +x, -y, +y, -z, +z.
@@ -96,9 +80,11 @@ __global__ void k_seed(T* __restrict__ phi, uint8_t* __restrict__ lab, SrcBatch<
     }
 }
 
+// One wave: FAR neighbours (F > 0) of a batch of sources become active and are
+// appended to segment `seg` of `out`.
 template <typename T, int ND>
 __global__ void k_seed_active(GridDims gd, const T* __restrict__ F, uint8_t* lab, SrcBatch<T> b,
-                              int* list, int* cnt) {
+                              SegList out, int seg) {
     const Grid g = make_grid(gd);
     int k = threadIdx.x;
     int items[6];
@@ -117,27 +103,27 @@ __global__ void k_seed_active(GridDims gd, const T* __restrict__ F, uint8_t* lab
             }
         }
     }
-    wave_append_mask<6>(list, cnt, items, mask);
+    const int c = __popc(mask);
+    const int incl = wave_incl_scan(c);
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    int base = 0;
+    if (lane_id() == 63) base = atomicAdd(out.count + seg, total);
+    base = __shfl(base, 63, 64);
+    int* dst = out.data + static_cast<size_t>(seg) * out.cap + base + incl - c;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        if (mask & (1u << j)) dst[__popc(mask & ((1u << j) - 1u))] = items[j];
+}
+
+__global__ void k_seg_clear(int* count, int nseg) {
+    for (int i = threadIdx.x; i < nseg; i += blockDim.x) count[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // STEP 2
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ int iter_prologue(const NodeIter<T>& a, unsigned long long* iters,
-                                             unsigned long long* evals, bool track_max) {
-    const int n = *a.cnt_cur;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.cnt_zero = 0;
-        if (n > 0) {
-            *iters += 1;
-            *evals += static_cast<unsigned long long>(n);
-            if (track_max && static_cast<unsigned long long>(n) > a.ctl->max_active)
-                a.ctl->max_active = static_cast<unsigned long long>(n);
-        }
-    }
-    return n;
-}
+constexpr int G = kNodeSegs;
 
 // Shared by the in-place and the synchronous-read apply kernels.
 template <typename T, int ND>
@@ -174,32 +160,64 @@ __device__ __forceinline__ uint32_t step2_apply_node(const NodeIter<T>& a, const
     return mask;
 }
 
+// Loads the list lengths, updates the per-iteration counters (block 0) and
+// returns this workgroup's slice.
+template <typename T>
+__device__ __forceinline__ int list_prologue(const NodeIter<T>& a, int* s_pref, bool step2, int& lo,
+                                             int& hi) {
+    const int n = seg_prefix<G>(a.cur.count, s_pref);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) {
+        const unsigned long long un = static_cast<unsigned long long>(n);
+        if (step2) {
+            a.ctl->iters2 += 1;
+            a.ctl->evals2 += un;
+            if (un > a.ctl->max_active) a.ctl->max_active = un;
+        } else {
+            a.ctl->iters3 += 1;
+            a.ctl->evals_rem += un;
+        }
+    }
+    if (!step2 && blockIdx.x == 0 && threadIdx.x == 0 && a.first)
+        a.ctl->remedy_init = static_cast<unsigned long long>(n);
+    seg_slice(n, G, lo, hi);
+    return n;
+}
+
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T h, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt;
     const Grid g = make_grid(gd);
-    const int n = iter_prologue(a, &a.ctl->iters2, &a.ctl->evals2, true);
-    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    SegAppender app{&s_cnt};
+    app.init();
+    int lo, hi;
+    list_prologue(a, s_pref, true, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
         const int k = base + threadIdx.x;
         int items[7];
         uint32_t mask = 0;
-        if (k < n) {
-            const int i = a.list_cur[k];
+        if (k < hi) {
+            const int i = seg_entry<G>(a.cur, s_pref, k);
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pi = a.phi[i];
             const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
             mask = step2_apply_node<T, ND>(a, g, i, pi, pt, eps, items);
         }
-        wave_append_mask<7>(a.list_next, a.cnt_next, items, mask);
+        app.push_mask<7>(a.next, items, mask);
     }
+    __syncthreads();
+    app.publish(a.next);
 }
 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_step2_eval(NodeIter<T> a, GridDims gd, T h) {
+    __shared__ int s_pref[G + 1];
     const Grid g = make_grid(gd);
-    const int n = iter_prologue(a, &a.ctl->iters2, &a.ctl->evals2, true);
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
-        const int i = a.list_cur[k];
+    int lo, hi;
+    list_prologue(a, s_pref, true, lo, hi);
+    for (int k = lo + static_cast<int>(threadIdx.x); k < hi; k += kBlock) {
+        const int i = seg_entry<G>(a.cur, s_pref, k);
         int x, y, z;
         decode<ND>(g, i, x, y, z);
         a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
@@ -208,18 +226,26 @@ __global__ __launch_bounds__(kBlock) void k_step2_eval(NodeIter<T> a, GridDims g
 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_step2_apply(NodeIter<T> a, GridDims gd, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt;
     const Grid g = make_grid(gd);
-    const int n = *a.cnt_cur;
-    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    SegAppender app{&s_cnt};
+    app.init();
+    const int n = seg_prefix<G>(a.cur.count, s_pref);
+    int lo, hi;
+    seg_slice(n, G, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
         const int k = base + threadIdx.x;
         int items[7];
         uint32_t mask = 0;
-        if (k < n) {
-            const int i = a.list_cur[k];
+        if (k < hi) {
+            const int i = seg_entry<G>(a.cur, s_pref, k);
             mask = step2_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, items);
         }
-        wave_append_mask<7>(a.list_next, a.cnt_next, items, mask);
+        app.push_mask<7>(a.next, items, mask);
     }
+    __syncthreads();
+    app.publish(a.next);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,19 +255,28 @@ template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_detect(GridDims gd, const T* __restrict__ F,
                                                    const T* __restrict__ phi,
                                                    const uint8_t* __restrict__ lab, T h, T eps,
-                                                   int* list, int* cnt) {
+                                                   SegList out) {
+    __shared__ int s_cnt;
     const Grid g = make_grid(gd);
-    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+    SegAppender app{&s_cnt};
+    app.init();
+    __syncthreads();
+    int lo, hi;
+    seg_slice(g.n, G, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
         const int i = base + threadIdx.x;
-        bool flag = false;
-        if (i < g.n && lab[i] != L_FIXED) {
+        int items[1] = {i};
+        uint32_t mask = 0;
+        if (i < hi && lab[i] != L_FIXED) {
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pt = eval_node<T, ND>(phi, F, g, i, x, y, z, h);
-            flag = pt < phi[i] - eps;
+            mask = pt < phi[i] - eps ? 1u : 0u;
         }
-        wave_append1(list, cnt, i, flag);
+        app.push_mask<1>(out, items, mask);
     }
+    __syncthreads();
+    app.publish(out);
 }
 
 // claim node q for the next remedy list (first claimer this iteration wins)
@@ -276,72 +311,81 @@ __device__ __forceinline__ uint32_t remedy_apply_node(const NodeIter<T>& a, cons
     return mask;
 }
 
+// Remedy iterations advance the stamp tag: the iteration with slot p reads
+// tag[p] and block 0 stores tag[p] + 1 into tag[p ^ 1] for the next one.
 template <typename T>
-__device__ __forceinline__ int remedy_prologue(const NodeIter<T>& a, uint32_t& tag) {
-    const int n = *a.cnt_cur;
-    tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.cnt_zero = 0;
-        a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
-        if (a.first) a.ctl->remedy_init = static_cast<unsigned long long>(n);
-        if (n > 0) {
-            a.ctl->iters3 += 1;
-            a.ctl->evals_rem += static_cast<unsigned long long>(n);
-        }
-    }
-    return n;
+__device__ __forceinline__ uint32_t remedy_tag(const NodeIter<T>& a, bool advance) {
+    const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
+    return tag;
 }
 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T h, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt;
     const Grid g = make_grid(gd);
-    uint32_t tag;
-    const int n = remedy_prologue(a, tag);
-    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    const uint32_t tag = remedy_tag(a, true);
+    SegAppender app{&s_cnt};
+    app.init();
+    int lo, hi;
+    list_prologue(a, s_pref, false, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
         const int k = base + threadIdx.x;
         int items[7];
         uint32_t mask = 0;
-        if (k < n) {
-            const int i = a.list_cur[k];
+        if (k < hi) {
+            const int i = seg_entry<G>(a.cur, s_pref, k);
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
             mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], pt, eps, tag, items);
         }
-        wave_append_mask<7>(a.list_next, a.cnt_next, items, mask);
+        app.push_mask<7>(a.next, items, mask);
     }
+    __syncthreads();
+    app.publish(a.next);
 }
 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_remedy_eval(NodeIter<T> a, GridDims gd, T h) {
+    __shared__ int s_pref[G + 1];
     const Grid g = make_grid(gd);
-    uint32_t tag;
-    const int n = remedy_prologue(a, tag);
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
-        const int i = a.list_cur[k];
+    remedy_tag(a, true);
+    int lo, hi;
+    list_prologue(a, s_pref, false, lo, hi);
+    for (int k = lo + static_cast<int>(threadIdx.x); k < hi; k += kBlock) {
+        const int i = seg_entry<G>(a.cur, s_pref, k);
         int x, y, z;
         decode<ND>(g, i, x, y, z);
         a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
     }
 }
 
-// The apply kernel of the synchronous mode reads the tag its eval kernel used
-// (the eval kernel already advanced the other slot).
+// The apply kernel of the synchronous mode uses the tag its eval kernel read.
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_remedy_apply(NodeIter<T> a, GridDims gd, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt;
     const Grid g = make_grid(gd);
-    const int n = *a.cnt_cur;
-    const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
-    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    const uint32_t tag = remedy_tag(a, false);
+    SegAppender app{&s_cnt};
+    app.init();
+    const int n = seg_prefix<G>(a.cur.count, s_pref);
+    int lo, hi;
+    seg_slice(n, G, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
         const int k = base + threadIdx.x;
         int items[7];
         uint32_t mask = 0;
-        if (k < n) {
-            const int i = a.list_cur[k];
+        if (k < hi) {
+            const int i = seg_entry<G>(a.cur, s_pref, k);
             mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, tag, items);
         }
-        wave_append_mask<7>(a.list_next, a.cnt_next, items, mask);
+        app.push_mask<7>(a.next, items, mask);
     }
+    __syncthreads();
+    app.publish(a.next);
 }
 
 template <typename T, int ND>
@@ -398,64 +442,65 @@ hipError_t launch_seed(T* phi, uint8_t* lab, const SrcBatch<T>& b, hipStream_t s
 
 template <typename T>
 hipError_t launch_seed_active(const GridDims& g, const T* F, uint8_t* lab, const SrcBatch<T>& b,
-                              int* list, int* cnt, hipStream_t s) {
+                              const SegList& out, int seg, hipStream_t s) {
     if (g.nd == 2)
         hipLaunchKernelGGL((k_seed_active<T, 2>), dim3(1), dim3(kMaxSrcBatch), 0, s, g, F, lab, b,
-                           list, cnt);
+                           out, seg);
     else
         hipLaunchKernelGGL((k_seed_active<T, 3>), dim3(1), dim3(kMaxSrcBatch), 0, s, g, F, lab, b,
-                           list, cnt);
+                           out, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_clear, dim3(1), dim3(kBlock), 0, s, count, nseg);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
-                        int blocks, hipStream_t s) {
+hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s) {
     if (det) {
         if (g.nd == 2) {
-            hipLaunchKernelGGL((k_step2_eval<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, h);
-            hipLaunchKernelGGL((k_step2_apply<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, eps);
+            hipLaunchKernelGGL((k_step2_eval<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h);
+            hipLaunchKernelGGL((k_step2_apply<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, eps);
         } else {
-            hipLaunchKernelGGL((k_step2_eval<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, h);
-            hipLaunchKernelGGL((k_step2_apply<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, eps);
+            hipLaunchKernelGGL((k_step2_eval<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h);
+            hipLaunchKernelGGL((k_step2_apply<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, eps);
         }
     } else {
         if (g.nd == 2)
-            hipLaunchKernelGGL((k_step2<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, h, eps);
+            hipLaunchKernelGGL((k_step2<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
         else
-            hipLaunchKernelGGL((k_step2<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, h, eps);
+            hipLaunchKernelGGL((k_step2<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, T h, T eps,
-                         int* list, int* cnt, hipStream_t s) {
+                         const SegList& out, hipStream_t s) {
     if (g.nd == 2)
-        hipLaunchKernelGGL((k_detect<T, 2>), dim3(dense_blocks(g.n)), dim3(kBlock), 0, s, g, F, phi,
-                           lab, h, eps, list, cnt);
+        hipLaunchKernelGGL((k_detect<T, 2>), dim3(G), dim3(kBlock), 0, s, g, F, phi, lab, h, eps, out);
     else
-        hipLaunchKernelGGL((k_detect<T, 3>), dim3(dense_blocks(g.n)), dim3(kBlock), 0, s, g, F, phi,
-                           lab, h, eps, list, cnt);
+        hipLaunchKernelGGL((k_detect<T, 3>), dim3(G), dim3(kBlock), 0, s, g, F, phi, lab, h, eps, out);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det,
-                         int blocks, hipStream_t s) {
+hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s) {
     if (det) {
         if (g.nd == 2) {
-            hipLaunchKernelGGL((k_remedy_eval<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, h);
-            hipLaunchKernelGGL((k_remedy_apply<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, eps);
+            hipLaunchKernelGGL((k_remedy_eval<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h);
+            hipLaunchKernelGGL((k_remedy_apply<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, eps);
         } else {
-            hipLaunchKernelGGL((k_remedy_eval<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, h);
-            hipLaunchKernelGGL((k_remedy_apply<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, eps);
+            hipLaunchKernelGGL((k_remedy_eval<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h);
+            hipLaunchKernelGGL((k_remedy_apply<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, eps);
         }
     } else {
         if (g.nd == 2)
-            hipLaunchKernelGGL((k_remedy<T, 2>), dim3(blocks), dim3(kBlock), 0, s, it, g, h, eps);
+            hipLaunchKernelGGL((k_remedy<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
         else
-            hipLaunchKernelGGL((k_remedy<T, 3>), dim3(blocks), dim3(kBlock), 0, s, it, g, h, eps);
+            hipLaunchKernelGGL((k_remedy<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
     }
     return hipGetLastError();
 }
@@ -486,12 +531,12 @@ hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
     template hipError_t launch_init<T>(const T*, T*, uint8_t*, uint32_t*, int, Ctl*, hipStream_t); \
     template hipError_t launch_seed<T>(T*, uint8_t*, const SrcBatch<T>&, hipStream_t);             \
     template hipError_t launch_seed_active<T>(const GridDims&, const T*, uint8_t*,                 \
-                                              const SrcBatch<T>&, int*, int*, hipStream_t);        \
-    template hipError_t launch_step2<T>(const GridDims&, const NodeIter<T>&, T, T, bool, int,      \
+                                              const SrcBatch<T>&, const SegList&, int, hipStream_t); \
+    template hipError_t launch_step2<T>(const GridDims&, const NodeIter<T>&, T, T, bool,           \
                                         hipStream_t);                                              \
     template hipError_t launch_detect<T>(const GridDims&, const T*, const T*, const uint8_t*, T, T, \
-                                         int*, int*, hipStream_t);                                 \
-    template hipError_t launch_remedy<T>(const GridDims&, const NodeIter<T>&, T, T, bool, int,     \
+                                         const SegList&, hipStream_t);                             \
+    template hipError_t launch_remedy<T>(const GridDims&, const NodeIter<T>&, T, T, bool,          \
                                          hipStream_t);                                             \
     template hipError_t launch_apply_local<T>(const GridDims&, const T*, const T*, T, T*,          \
                                               hipStream_t);

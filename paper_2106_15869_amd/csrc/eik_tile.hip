@@ -14,17 +14,23 @@
 //     tile that still holds active nodes schedules itself.
 //   remedy detection (STEP 3, first part): one dense pass over all tiles;
 //     a tile with any node whose phi~ < phi - eps enters the remedy list.
-//   remedy loop (STEP 3): every non-source node of a listed tile is
-//     recomputed until nothing in the tile changes (the remedy loop restricted
-//     to the tile); a change on a tile face schedules the tile across it.
+//   remedy loop (STEP 3): the remedy rule of Section 3.1.2 restricted to the
+//     tile: recompute the flagged nodes, take the drops, flag the changed
+//     nodes and their in-tile neighbours for the next inner iteration, until
+//     no flagged node changes.  A tile enters with all nodes flagged (first
+//     visit) or with the nodes on the faces whose neighbour tile changed; a
+//     change on a tile face marks that face dirty in the tile across it and
+//     schedules it.
 // Within an inner iteration all phi~ are computed before any is applied (two
 // LDS phases), so a tile's iterations are synchronous; tiles of one launch see
-// each other's values only through the halo staged at the start.
+// each other's values only through the halo staged at the start.  Tile lists
+// are segmented per workgroup (eik_seglist.hpp).
 #include <utility>
 #include <vector>
 
 #include "eik_device.hpp"
 #include "eik_host.hpp"
+#include "eik_seglist.hpp"
 #include "eik_tile.hpp"
 
 namespace eik {
@@ -33,6 +39,10 @@ namespace {
 
 // LDS label byte: bits 0-1 state, bit 2 passable (F > 0), bit 3 outside grid.
 constexpr uint8_t kPass = 4u, kOut = 8u;
+// Workgroups per tile launch (one list segment each).
+constexpr int GT = 1024;
+// Dirty-face mask bit meaning "recheck every node of the tile".
+constexpr uint32_t kAllFaces = 64u;
 
 struct TileGeom {
     int nx, ny, nz;   // grid
@@ -46,11 +56,9 @@ struct TileIter {
     T* phi;
     uint8_t* lab;
     uint32_t* tstamp;
-    const int* list_cur;
-    int* list_next;
-    int* cnt_cur;
-    int* cnt_next;
-    int* cnt_zero;
+    uint32_t* tmask;   // per tile: dirty faces (bit d) or kAllFaces
+    SegList cur;
+    SegList next;
     Ctl* ctl;
     int tag_slot;
     int phase;  // 0 update step, 1 remedy loop
@@ -62,9 +70,6 @@ __device__ __forceinline__ bool claim_tile(uint32_t* tstamp, int t, uint32_t tag
     return atomicMax(tstamp + t, tag) < tag;
 }
 
-__device__ __forceinline__ void push_tile(uint32_t* tstamp, int t, uint32_t tag, int* list, int* cnt) {
-    if (claim_tile(tstamp, t, tag)) list[atomicAdd(cnt, 1)] = t;
-}
 
 template <int ND, int TX, int TY, int TZ>
 struct Shape {
@@ -85,6 +90,7 @@ struct Owned {
     int L[NPT];      // LDS index (with halo)
     int face[NPT];   // bit d set: node on the tile face in direction d (-x,+x,-y,+y,-z,+z)
                      // and the grid continues across it
+    int edge[NPT];   // bit d set: node on the tile face in direction d
     T H[NPT];
     bool ok[NPT];
 };
@@ -124,6 +130,16 @@ __device__ __forceinline__ void own_nodes(const TileGeom& g, int x0, int y0, int
         o.ok[r] = n < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
         o.G[r] = (gz * g.ny + gy) * g.nx + gx;
         o.L[r] = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
+        int e = 0;
+        if (x == 0) e |= 1;
+        if (x == TX - 1) e |= 2;
+        if (y == 0) e |= 4;
+        if (y == TY - 1) e |= 8;
+        if (ND == 3) {
+            if (z == 0) e |= 16;
+            if (z == TZ - 1) e |= 32;
+        }
+        o.edge[r] = e;
         int f = 0;
         if (x == 0 && gx > 0) f |= 1;
         if (x == TX - 1 && gx + 1 < g.nx) f |= 2;
@@ -174,24 +190,34 @@ __device__ __forceinline__ int neighbour_tile(const TileGeom& g, int t, int d) {
     }
 }
 
+// Tag chain: launch with slot p reads tag[p] and stores tag[p] + 1 into
+// tag[p ^ 1]; tiles it schedules are claimed with tag[p] + 1.
 template <typename T>
-__device__ __forceinline__ uint32_t launch_prologue(const TileIter<T>& a, int n) {
+__device__ __forceinline__ uint32_t launch_tag(const TileIter<T>& a) {
     const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
+    return tag + 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void launch_stats(const TileIter<T>& a, int n) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.cnt_zero = 0;
-        a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
+        const unsigned long long un = static_cast<unsigned long long>(n);
         if (n > 0) {
             if (a.phase == 0) {
                 a.ctl->iters2 += 1;
-                if (static_cast<unsigned long long>(n) > a.ctl->max_active)
-                    a.ctl->max_active = static_cast<unsigned long long>(n);
+                if (un > a.ctl->max_active) a.ctl->max_active = un;
             } else {
                 a.ctl->iters3 += 1;
             }
         }
-        if (a.first) a.ctl->remedy_init = static_cast<unsigned long long>(n);
+        if (a.first) a.ctl->remedy_init = un;
     }
-    return tag + 1;  // claims made by this launch build the next list
+}
+
+__device__ __forceinline__ void push_tile(const SegList& out, SegAppender& app, uint32_t* tstamp, int t,
+                                          uint32_t tag) {
+    if (claim_tile(tstamp, t, tag)) app.push_one(out, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,14 +229,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
+    __shared__ int s_pref[GT + 1];
+    __shared__ int s_cnt;
     __shared__ int s_face;
     __shared__ int s_evals;
     const T inf = pos_inf<T>();
-    const int n = *a.cnt_cur;
-    const uint32_t ntag = launch_prologue(a, n);
+    SegAppender app{&s_cnt};
+    app.init();
+    const uint32_t ntag = launch_tag(a);
+    const int n = seg_prefix<GT>(a.cur.count, s_pref);
+    launch_stats(a, n);
+    int lo, hi;
+    seg_slice(n, GT, lo, hi);
     unsigned long long evals = 0;
-    for (int e = blockIdx.x; e < n; e += gridDim.x) {
-        const int t = a.list_cur[e];
+    for (int e = lo; e < hi; ++e) {
+        const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
@@ -303,14 +336,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         if (my_evals) atomicAdd(&s_evals, my_evals);
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (any_active) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+            if (any_active) push_tile(a.next, app, a.tstamp, t, ntag);
             const int fm = s_face;
             for (int d = 0; d < 2 * ND; ++d)
-                if (fm & (1 << d)) push_tile(a.tstamp, neighbour_tile(g, t, d), ntag, a.list_next, a.cnt_next);
+                if (fm & (1 << d)) push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
             evals += static_cast<unsigned long long>(s_evals);
         }
         __syncthreads();
     }
+    app.publish(a.next);
     if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals2, evals);
 }
 
@@ -322,22 +356,33 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
-    const uint32_t ntag = launch_prologue(a, 0);
-    const int t = blockIdx.x;
-    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
-    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
-    stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
-    Owned<T, S::NPT> o;
-    own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
-    __syncthreads();
-    bool flag = false;
+    __shared__ int s_cnt;
+    SegAppender app{&s_cnt};
+    app.init();
+    const uint32_t ntag = launch_tag(a);
+    int lo, hi;
+    seg_slice(g.ntiles, GT, lo, hi);
+    for (int t = lo; t < hi; ++t) {
+        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        Owned<T, S::NPT> o;
+        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        __syncthreads();
+        bool flag = false;
 #pragma unroll
-    for (int r = 0; r < S::NPT; ++r) {
-        if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
-        const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
-        flag |= pt < sphi[o.L[r]] - eps;
+        for (int r = 0; r < S::NPT; ++r) {
+            if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
+            const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
+            flag |= pt < sphi[o.L[r]] - eps;
+        }
+        if (__syncthreads_or(flag) && threadIdx.x == 0) {
+            atomicOr(a.tmask + t, kAllFaces);
+            push_tile(a.next, app, a.tstamp, t, ntag);
+        }
     }
-    if (__syncthreads_or(flag) && threadIdx.x == 0) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+    __syncthreads();
+    app.publish(a.next);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,14 +394,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
+    __shared__ uint8_t snf[S::NL];  // flags for the next inner iteration
+    __shared__ int s_pref[GT + 1];
+    __shared__ int s_cnt;
     __shared__ int s_face;
     __shared__ int s_evals;
+    __shared__ uint32_t s_mask;
     const T inf = pos_inf<T>();
-    const int n = *a.cnt_cur;
-    const uint32_t ntag = launch_prologue(a, n);
+    SegAppender app{&s_cnt};
+    app.init();
+    const uint32_t ntag = launch_tag(a);
+    const int n = seg_prefix<GT>(a.cur.count, s_pref);
+    launch_stats(a, n);
+    int lo, hi;
+    seg_slice(n, GT, lo, hi);
     unsigned long long evals = 0;
-    for (int e = blockIdx.x; e < n; e += gridDim.x) {
-        const int t = a.list_cur[e];
+    for (int e = lo; e < hi; ++e) {
+        const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
@@ -365,16 +419,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         if (threadIdx.x == 0) {
             s_face = 0;
             s_evals = 0;
+            s_mask = atomicExch(a.tmask + t, 0u);
         }
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r)
+            if (o.ok[r]) snf[o.L[r]] = 0;
         __syncthreads();
-        bool live[S::NPT];
+        const uint32_t m = s_mask;
+        bool live[S::NPT], fl[S::NPT];
         T phi0[S::NPT];
-        int nlive = 0;
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             live[r] = o.ok[r] && (sl[o.L[r]] & 3u) != L_FIXED;
             phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
-            nlive += live[r] ? 1 : 0;
+            fl[r] = live[r] && ((m & kAllFaces) || (o.face[r] & static_cast<int>(m)));
         }
         bool pending = false;
         int my_evals = 0;
@@ -386,24 +444,37 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             for (int r = 0; r < S::NPT; ++r) {
                 ch[r] = false;
                 pt[r] = inf;
-                if (live[r]) {
+                if (fl[r]) {
                     pt[r] = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
                     ch[r] = pt[r] < sphi[o.L[r]] - eps;
                     has |= ch[r];
+                    ++my_evals;
                 }
             }
-            my_evals += nlive;
             pending = __syncthreads_or(has);
             if (!pending || it == inner) break;
             int fm = 0;
 #pragma unroll
             for (int r = 0; r < S::NPT; ++r) {
                 if (!ch[r]) continue;
-                sphi[o.L[r]] = pt[r];
+                const int L = o.L[r];
+                sphi[L] = pt[r];
+                snf[L] = 1;
+#pragma unroll
+                for (int d = 0; d < 2 * ND; ++d)
+                    if (!(o.edge[r] & (1 << d))) snf[L + lds_offset<ND, TX, TY, TZ>(d)] = 1;
                 fm |= o.face[r];
             }
             if (fm) atomicOr(&s_face, fm);
             __syncthreads();
+#pragma unroll
+            for (int r = 0; r < S::NPT; ++r) {
+                fl[r] = false;
+                if (o.ok[r]) {
+                    fl[r] = live[r] && snf[o.L[r]];
+                    snf[o.L[r]] = 0;
+                }
+            }
         }
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
@@ -414,14 +485,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         if (my_evals) atomicAdd(&s_evals, my_evals);
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (pending) push_tile(a.tstamp, t, ntag, a.list_next, a.cnt_next);
+            if (pending) {
+                atomicOr(a.tmask + t, kAllFaces);
+                push_tile(a.next, app, a.tstamp, t, ntag);
+            }
             const int fm = s_face;
-            for (int d = 0; d < 2 * ND; ++d)
-                if (fm & (1 << d)) push_tile(a.tstamp, neighbour_tile(g, t, d), ntag, a.list_next, a.cnt_next);
+            for (int d = 0; d < 2 * ND; ++d) {
+                if (!(fm & (1 << d))) continue;
+                const int tn = neighbour_tile(g, t, d);
+                atomicOr(a.tmask + tn, 1u << (d ^ 1));  // the face of tn shared with t
+                push_tile(a.next, app, a.tstamp, tn, ntag);
+            }
             evals += static_cast<unsigned long long>(s_evals);
         }
         __syncthreads();
     }
+    app.publish(a.next);
     if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals_rem, evals);
 }
 
@@ -432,10 +511,11 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
 }
 
-// Initial tile list: tiles holding a grid neighbour of a source (claimed with tag 1).
+// Initial tile list: tiles holding a grid neighbour of a source (claimed with
+// tag 1), appended to segment `seg`.
 template <typename T>
 __global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcBatch<T> b,
-                             uint32_t* tstamp, int* list, int* cnt) {
+                             uint32_t* tstamp, SegList out, int seg) {
     const int k = threadIdx.x;
     if (k >= b.count) return;
     const int i = b.idx[k];
@@ -445,8 +525,20 @@ __global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcB
         const int X = x + dx[d], Y = y + dy[d], Z = z + dz[d];
         if (X < 0 || X >= g.nx || Y < 0 || Y >= g.ny || Z < 0 || Z >= g.nz) continue;
         const int t = ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_);
-        push_tile(tstamp, t, 1u, list, cnt);
+        if (claim_tile(tstamp, t, 1u)) out.data[static_cast<size_t>(seg) * out.cap + atomicAdd(out.count + seg, 1)] = t;
     }
+}
+
+// Initial tile list holding every tile (used when there are many sources):
+// workgroup b lists its contiguous slice of tiles in its own segment.
+__global__ void k_seed_all_tiles(int ntiles, uint32_t* tstamp, SegList out) {
+    int lo, hi;
+    seg_slice(ntiles, GT, lo, hi);
+    for (int t = lo + static_cast<int>(threadIdx.x); t < hi; t += kBlock) {
+        tstamp[t] = 1u;
+        out.data[static_cast<size_t>(blockIdx.x) * out.cap + (t - lo)] = t;
+    }
+    if (threadIdx.x == 0) out.count[blockIdx.x] = hi - lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -483,10 +575,14 @@ struct TileWs {
     Ctl* ctl;
     uint8_t* lab;
     uint32_t* tstamp;
-    int* list[2];
+    uint32_t* tmask;
+    SegList seg[2];
     size_t bytes;
 };
 
+// A segment holds what one workgroup can schedule from its slice of at most
+// ceil(ntiles / GT) tiles (itself and six face neighbours each), plus room for
+// source seeding.
 TileWs tile_layout(char* base, int64_t n, int ntiles) {
     TileWs w{};
     size_t off = 0;
@@ -495,31 +591,36 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
         off = align_up(off + b, 256);
         return p;
     };
+    const int cap = 7 * ((ntiles + GT - 1) / GT) + 512;
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
-    w.list[0] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
-    w.list[1] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
+    w.tmask = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
+    for (int k = 0; k < 2; ++k) {
+        w.seg[k].cap = cap;
+        w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(GT)));
+        w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * GT));
+    }
     w.bytes = off;
     return w;
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
 struct TileKernels {
-    static hipError_t update(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner, int blocks,
+    static hipError_t update(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner,
                              hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(blocks), dim3(kBlock), 0, s, a, g, h,
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
                            eps, inner);
         return hipGetLastError();
     }
     static hipError_t detect(const TileIter<T>& a, const TileGeom& g, T h, T eps, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(g.ntiles), dim3(kBlock), 0, s, a, g, h,
+        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
                            eps);
         return hipGetLastError();
     }
-    static hipError_t remedy(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner, int blocks,
+    static hipError_t remedy(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner,
                              hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(blocks), dim3(kBlock), 0, s, a, g, h,
+        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
                            eps, inner);
         return hipGetLastError();
     }
@@ -527,9 +628,9 @@ struct TileKernels {
 
 template <typename T>
 struct TileOps {
-    hipError_t (*update)(const TileIter<T>&, const TileGeom&, T, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*update)(const TileIter<T>&, const TileGeom&, T, T, int, hipStream_t) = nullptr;
     hipError_t (*detect)(const TileIter<T>&, const TileGeom&, T, T, hipStream_t) = nullptr;
-    hipError_t (*remedy)(const TileIter<T>&, const TileGeom&, T, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*remedy)(const TileIter<T>&, const TileGeom&, T, T, int, hipStream_t) = nullptr;
 };
 
 template <typename T, int ND, int TX, int TY, int TZ>
@@ -580,15 +681,16 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     TileWs w = tile_layout(ws, gd.n, g.ntiles);
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * static_cast<int64_t>(gd.n) + 64;
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
-    const int blocks = std::min(g.ntiles, 2048);
     int64_t launched = 0;
 
     HIP_TRY(launch_ctl_init(w.ctl, s));
     HIP_TRY(launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s));
-    hipLaunchKernelGGL(k_zero_u32, dim3(std::min((g.ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
-                       w.tstamp, g.ntiles);
+    // tile stamps and dirty-face masks are adjacent: clear both
+    hipLaunchKernelGGL(k_zero_u32, dim3(std::min((2 * g.ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0,
+                       s, w.tstamp, static_cast<int>(w.tmask - w.tstamp) + g.ntiles);
     HIP_TRY(hipGetLastError());
-    launched += 3;
+    HIP_TRY(launch_seg_clear(w.seg[0].count, GT, s));
+    launched += 4;
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> b{};
@@ -600,12 +702,17 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         batches.push_back(b);
     }
     for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
-    for (auto& b : batches) {
-        hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz, b,
-                           w.tstamp, w.list[0], &w.ctl->cnt[0]);
-        HIP_TRY(hipGetLastError());
+    launched += static_cast<int64_t>(batches.size());
+    if (batches.size() == 1) {
+        // tiles next to the sources (at most 6 * 64 tiles: fits one segment)
+        hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz,
+                           batches[0], w.tstamp, w.seg[0], 0);
+    } else {
+        // many sources: start from every tile; tiles with nothing to do drop out
+        hipLaunchKernelGGL(k_seed_all_tiles, dim3(GT), dim3(kBlock), 0, s, g.ntiles, w.tstamp, w.seg[0]);
     }
-    launched += 2 * static_cast<int64_t>(batches.size());
+    HIP_TRY(hipGetLastError());
+    launched += 1;
 
     const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
     int64_t gl = 0;  // launches in the tag chain so far (selects the tag slot)
@@ -615,37 +722,33 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.phi = phi;
         a.lab = w.lab;
         a.tstamp = w.tstamp;
-        a.list_cur = w.list[t & 1];
-        a.list_next = w.list[(t + 1) & 1];
-        a.cnt_cur = &w.ctl->cnt[t % 3];
-        a.cnt_next = &w.ctl->cnt[(t + 1) % 3];
-        a.cnt_zero = &w.ctl->cnt[(t + 2) % 3];
+        a.tmask = w.tmask;
+        a.cur = w.seg[t & 1];
+        a.next = w.seg[(t + 1) & 1];
         a.ctl = w.ctl;
         a.tag_slot = static_cast<int>((gl + t) & 1);
         a.phase = phase;
         a.first = (phase == 1 && t == 0) ? 1 : 0;
         return a;
     };
-    auto counter = [&](int64_t t) { return &w.ctl->cnt[t % 3]; };
+    auto counts = [&](int64_t t) { return w.seg[t & 1].count; };
 
     int64_t n2 = 0;
-    eik_status rc = run_loop([&](int64_t t) { return k.update(iter_args(t, 0), g, hT, eT, inner, blocks, s); },
-                             counter, cap, async, s, &n2);
+    eik_status rc = run_loop([&](int64_t t) { return k.update(iter_args(t, 0), g, hT, eT, inner, s); },
+                             counts, GT, cap, async, s, &n2);
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
-        HIP_TRY(launch_reset_counters(w.ctl, s));
-        // detection appends into list 0 through counter 0 (t = -1 -> next = 0)
+        // detection writes list 0 (consumed by remedy launch 0)
         TileIter<T> d = iter_args(0, 1);
-        d.list_next = w.list[0];
-        d.cnt_next = &w.ctl->cnt[0];
-        d.cnt_zero = &w.ctl->cnt[2];
+        d.first = 0;
+        d.next = w.seg[0];
         HIP_TRY(k.detect(d, g, hT, eT, s));
         gl += 1;
-        launched += 2;
+        launched += 1;
         int64_t n3 = 0;
-        rc = run_loop([&](int64_t t) { return k.remedy(iter_args(t, 1), g, hT, eT, inner, blocks, s); },
-                      counter, cap, async, s, &n3);
+        rc = run_loop([&](int64_t t) { return k.remedy(iter_args(t, 1), g, hT, eT, inner, s); },
+                      counts, GT, cap, async, s, &n3);
         launched += n3;
     }
     if (async) return rc;
