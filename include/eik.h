@@ -85,6 +85,10 @@ typedef struct {
     int64_t remedy_initial; /* nodes (node-list) or tiles (tile) flagged by detection */
     int64_t max_active;     /* peak active-list length (nodes or tiles) */
     int64_t launches;       /* kernel launches enqueued */
+    int64_t tile_visits_step2;  /* tile variant: tiles processed in the update step */
+    int64_t tile_visits_step3;  /* tile variant: tiles processed in the remedy loop */
+    int64_t inner_step2;        /* tile variant: inner iterations summed over visits */
+    int64_t inner_step3;
 } eik_stats;
 
 typedef struct {
@@ -142,16 +146,22 @@ eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim, const i
  * eik_adjoint -- gradient of a loss L(phi) with respect to F at a converged
  * solution phi of eik_solve (same F, h, sources).  At the solution each
  * reached non-source node satisfies sum_k w_ik^2 = (h/F_i)^2 over its upwind
- * axes (w_ik = phi_i - phi_upwind); the linearised system is transposed and
- * solved downwind-to-upwind:
+ * axes (w_ik = phi_i - phi_upwind, a neighbour on the lower-index side on a
+ * tie); the linearised system is transposed and solved downwind-to-upwind:
  *   lambda = dL/dphi + M^T lambda,  M_ij = w_ij / W_i,  W_i = sum_k w_ik,
  *   dL/dF_i = -lambda_i (h/F_i)^2 / (F_i W_i);  0 at sources and +inf nodes.
- *   dL_dphi device input (N), dL_dF_out device output (N).
+ * (Not in the paper: the derivative of the Eq 4 / Eq 6 fixed point.)
+ *   F, phi, dL_dphi device inputs (N); dL_dF_out device output (N, no alias).
+ *   opt: dtype, stream, workspace (eik_adjoint_workspace_size bytes; NULL ->
+ *   allocated per call), max_iters, inner_iters, stats, EIK_FLAG_ASYNC.
  * Errors as eik_solve.
  */
 eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
                        double h, const int64_t* sources, int64_t n_sources,
                        const void* dL_dphi, void* dL_dF_out, const eik_options* opt);
+
+/* Device workspace (bytes) eik_adjoint needs; 0 on invalid arguments. */
+size_t eik_adjoint_workspace_size(int32_t ndim, const int64_t* dims, const eik_options* opt);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_status_string(eik_status s);

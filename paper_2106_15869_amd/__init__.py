@@ -47,13 +47,15 @@ VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
 
 # Entry points declared in include/eik.h
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
-           "eik_adjoint", "eik_status_string", "eik_last_error", "eik_abi_version")
+           "eik_adjoint", "eik_adjoint_workspace_size", "eik_status_string", "eik_last_error",
+           "eik_abi_version")
 
 
 class EikStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
-        "remedy_initial", "max_active", "launches")]
+        "remedy_initial", "max_active", "launches", "tile_visits_step2", "tile_visits_step3",
+        "inner_step2", "inner_step3")]
 
     def to_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -112,6 +114,8 @@ def _load():
     lib.eik_apply_local.argtypes = [P, P, i32, P, d, P, OP]
     lib.eik_adjoint.restype = ctypes.c_int
     lib.eik_adjoint.argtypes = [P, P, i32, P, d, P, i64, P, P, OP]
+    lib.eik_adjoint_workspace_size.restype = ctypes.c_size_t
+    lib.eik_adjoint_workspace_size.argtypes = [i32, P, OP]
     lib.eik_status_string.restype = ctypes.c_char_p
     lib.eik_status_string.argtypes = [ctypes.c_int]
     lib.eik_last_error.restype = ctypes.c_char_p
@@ -267,7 +271,14 @@ def apply_local(F, phi, h: float, out=None):
     return res
 
 
-def adjoint(F, phi, h: float, sources, dL_dphi, out=None):
+def eik_adjoint_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] = None) -> int:
+    dims = _dims(shape)
+    return int(_load().eik_adjoint_workspace_size(len(dims), _np_ptr(dims),
+                                                  ctypes.byref(opt) if opt is not None else None))
+
+
+def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats: bool = False,
+            stream=None):
     """dL/dF at the converged solution phi (same F, h, sources)."""
     torch = _torch()
     for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
@@ -275,7 +286,17 @@ def adjoint(F, phi, h: float, sources, dL_dphi, out=None):
         if t.shape != F.shape or t.dtype != F.dtype:
             raise ValueError(f"{n} must match F in shape and dtype")
     opt = make_options(_dtype_code(F))
-    opt.stream = torch.cuda.current_stream(F.device).cuda_stream
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    need = eik_adjoint_workspace_size(F.shape, opt)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    elif workspace.numel() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    st = EikStats()
+    opt.stats = ctypes.pointer(st)
     res = out if out is not None else torch.empty_like(F)
     dims = _dims(F.shape)
     src = _sources_array(sources, F.shape)
@@ -284,4 +305,43 @@ def adjoint(F, phi, h: float, sources, dL_dphi, out=None):
                                  _np_ptr(src), len(src), dL_dphi.data_ptr(), res.data_ptr(),
                                  ctypes.byref(opt))
     _check(rc)
-    return res
+    return (res, st.to_dict()) if stats else res
+
+
+def _make_eikonal_fn():
+    torch = _torch()
+
+    class EikonalFn(torch.autograd.Function):
+        """phi = EikonalFn.apply(F, h, sources[, variant]) with dL/dF from eik_adjoint."""
+
+        @staticmethod
+        def forward(ctx, F, h, sources, variant="tile"):
+            Fc = F.detach().contiguous()
+            phi = solve(Fc, h, sources, variant=variant)
+            ctx.save_for_backward(Fc, phi)
+            ctx.h = float(h)
+            ctx.sources = _sources_array(sources, F.shape)
+            return phi
+
+        @staticmethod
+        def backward(ctx, grad_phi):
+            Fc, phi = ctx.saved_tensors
+            g = grad_phi.contiguous()
+            # unreached nodes carry no gradient (their phi is +inf)
+            g = torch.where(torch.isfinite(phi), g, torch.zeros_like(g))
+            dF = adjoint(Fc, phi, ctx.h, ctx.sources, g)
+            return dF, None, None, None
+
+    return EikonalFn
+
+
+_EikonalFn = None
+
+
+def __getattr__(name):
+    global _EikonalFn
+    if name == "EikonalFn":
+        if _EikonalFn is None:
+            _EikonalFn = _make_eikonal_fn()
+        return _EikonalFn
+    raise AttributeError(name)

@@ -337,6 +337,14 @@ EIK_API eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim,
     return EIK_OK;
 }
 
+EIK_API size_t eik_adjoint_workspace_size(int32_t ndim, const int64_t* dims, const eik_options* opt) {
+    Problem P;
+    if (check_shape(ndim, dims, P) != EIK_OK) return 0;
+    eik_options o = resolve(opt);
+    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64) return 0;
+    return adjoint_workspace_bytes(P.g, o);
+}
+
 EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
                                double h, const int64_t* sources, int64_t n_sources,
                                const void* dL_dphi, void* dL_dF_out, const eik_options* opt) {
@@ -347,9 +355,30 @@ EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, con
     eik_options o = resolve(opt);
     if ((rc = check_options(o))) return rc;
     if (!F || !phi || !dL_dphi || !dL_dF_out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
+    if (dL_dF_out == F || dL_dF_out == phi || dL_dF_out == dL_dphi)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "dL_dF_out must not alias the inputs");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
     if ((rc = check_sources(P, sources, n_sources, nullptr))) return rc;
-    return fail(EIK_ERR_UNSUPPORTED, "adjoint not available in this build");
+    const size_t need = adjoint_workspace_bytes(P.g, o);
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    OwnedWs owned;
+    char* ws = static_cast<char*>(o.workspace);
+    if (ws) {
+        if (o.workspace_bytes < need) return fail(EIK_ERR_OUT_OF_MEMORY, "workspace too small");
+    } else {
+        if (hipMallocAsync(&owned.p, need, s) != hipSuccess)
+            return fail(EIK_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        owned.s = s;
+        ws = static_cast<char*>(owned.p);
+    }
+    auto src = dedupe_sources(sources, nullptr, n_sources);
+    if (o.dtype == EIK_FLOAT64)
+        return adjoint_solve<double>(P.g, static_cast<const double*>(F), static_cast<const double*>(phi), h,
+                                     src, static_cast<const double*>(dL_dphi),
+                                     static_cast<double*>(dL_dF_out), o, ws, s, o.stats);
+    return adjoint_solve<float>(P.g, static_cast<const float*>(F), static_cast<const float*>(phi), h, src,
+                                static_cast<const float*>(dL_dphi), static_cast<float*>(dL_dF_out), o, ws,
+                                s, o.stats);
 }
 
 EIK_API const char* eik_status_string(eik_status s) {

@@ -17,7 +17,7 @@ struct Ctl {
     int tag[2];       // remedy stamp tags, alternating by iteration parity
     int pad;
     unsigned long long iters2, iters3, evals2, evals_det, evals_rem, remedy_init, max_active;
-    unsigned long long pad2;
+    unsigned long long visits2, visits3, inner2, inner3;
 };
 
 constexpr int kMaxSrcBatch = 64;

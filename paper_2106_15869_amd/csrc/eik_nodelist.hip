@@ -413,6 +413,7 @@ __global__ void k_ctl_init(Ctl* ctl) {
         ctl->tag[1] = 1;
         ctl->iters2 = ctl->iters3 = ctl->evals2 = ctl->evals_det = ctl->evals_rem = 0;
         ctl->remedy_init = ctl->max_active = 0;
+        ctl->visits2 = ctl->visits3 = ctl->inner2 = ctl->inner3 = 0;
     }
 }
 

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     launch_stats(a, n);
     int lo, hi;
     seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0;
+    unsigned long long evals = 0, inner_sum = 0;
     for (int e = lo; e < hi; ++e) {
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
@@ -279,32 +279,28 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             if (act) sl[o.L[r]] = (me & ~3u) | L_ACTIVE;
         }
         __syncthreads();
+        // Inner iterations, values updated in place in LDS: one barrier each.
+        // A node activated by a neighbour during an iteration is picked up in
+        // the same or the next one; reads racing with updates see either value,
+        // both upper bounds of the solution.
         bool any_active = false;
         int my_evals = 0;
-        for (int it = 0;; ++it) {
-            T pt[S::NPT];
-            bool act[S::NPT];
+        int it = 0;
+        for (;; ++it) {
             bool has = false;
+            int fm = 0;
 #pragma unroll
             for (int r = 0; r < S::NPT; ++r) {
-                act[r] = o.ok[r] && (sl[o.L[r]] & 3u) == L_ACTIVE;
-                pt[r] = inf;
-                if (act[r]) {
-                    pt[r] = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
-                    has = true;
-                }
-            }
-            any_active = __syncthreads_or(has);
-            if (!any_active || it == inner) break;
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                if (!act[r]) continue;
-                ++my_evals;
+                if (!o.ok[r]) continue;
                 const int L = o.L[r];
+                if ((sl[L] & 3u) != L_ACTIVE) continue;
+                has = true;
+                if (it == inner) continue;  // cap reached: leave it active
+                ++my_evals;
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, L, o.H[r]);
                 const T cur = sphi[L];
-                if (pt[r] < inf && cur - pt[r] <= eps) {
+                if (pt < inf && cur - pt <= eps) {
                     sl[L] = (sl[L] & ~3u) | L_CONV;
-                    int fm = 0;
 #pragma unroll
                     for (int d = 0; d < 2 * ND; ++d) {
                         const int q = L + lds_offset<ND, TX, TY, TZ>(d);
@@ -315,14 +311,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
                             sl[q] = (nb & ~3u) | L_ACTIVE;
                         }
                     }
-                    if (fm) atomicOr(&s_face, fm);
-                } else if (!(pt[r] < inf)) {
+                } else if (!(pt < inf)) {
                     sl[L] = (sl[L] & ~3u) | L_FAR;
-                } else if (pt[r] < cur) {
-                    sphi[L] = pt[r];
+                } else if (pt < cur) {
+                    sphi[L] = pt;
                 }
             }
-            __syncthreads();
+            if (fm) atomicOr(&s_face, fm);
+            any_active = __syncthreads_or(has);
+            if (!any_active || it == inner) break;
         }
         // write back what changed
 #pragma unroll
@@ -341,11 +338,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             for (int d = 0; d < 2 * ND; ++d)
                 if (fm & (1 << d)) push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
             evals += static_cast<unsigned long long>(s_evals);
+            inner_sum += static_cast<unsigned long long>(it);
         }
         __syncthreads();
     }
     app.publish(a.next);
-    if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals2, evals);
+    if (threadIdx.x == 0 && hi > lo) {
+        atomicAdd(&a.ctl->evals2, evals);
+        atomicAdd(&a.ctl->visits2, static_cast<unsigned long long>(hi - lo));
+        atomicAdd(&a.ctl->inner2, inner_sum);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
-    __shared__ uint8_t snf[S::NL];  // flags for the next inner iteration
+    __shared__ uint8_t snf[2][S::NL];  // flags for the next inner iteration (double buffered)
     __shared__ int s_pref[GT + 1];
     __shared__ int s_cnt;
     __shared__ int s_face;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     launch_stats(a, n);
     int lo, hi;
     seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0;
+    unsigned long long evals = 0, inner_sum = 0;
     for (int e = lo; e < hi; ++e) {
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         }
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r)
-            if (o.ok[r]) snf[o.L[r]] = 0;
+            if (o.ok[r]) snf[0][o.L[r]] = snf[1][o.L[r]] = 0;
         __syncthreads();
         const uint32_t m = s_mask;
         bool live[S::NPT], fl[S::NPT];
@@ -434,45 +436,41 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
             fl[r] = live[r] && ((m & kAllFaces) || (o.face[r] & static_cast<int>(m)));
         }
+        // Remedy iterations in place: a flagged node that drops takes the new
+        // value at once and flags itself and its in-tile neighbours in buffer
+        // it & 1, which every lane drains for its own nodes after the barrier.
         bool pending = false;
         int my_evals = 0;
-        for (int it = 0;; ++it) {
-            T pt[S::NPT];
-            bool ch[S::NPT];
+        int it = 0;
+        for (;; ++it) {
             bool has = false;
+            int fm = 0;
+            uint8_t* mark = snf[it & 1];
 #pragma unroll
             for (int r = 0; r < S::NPT; ++r) {
-                ch[r] = false;
-                pt[r] = inf;
-                if (fl[r]) {
-                    pt[r] = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
-                    ch[r] = pt[r] < sphi[o.L[r]] - eps;
-                    has |= ch[r];
-                    ++my_evals;
+                if (!fl[r]) continue;
+                ++my_evals;
+                const int L = o.L[r];
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, L, o.H[r]);
+                if (pt < sphi[L] - eps) {
+                    sphi[L] = pt;
+                    has = true;
+                    mark[L] = 1;
+#pragma unroll
+                    for (int d = 0; d < 2 * ND; ++d)
+                        if (!(o.edge[r] & (1 << d))) mark[L + lds_offset<ND, TX, TY, TZ>(d)] = 1;
+                    fm |= o.face[r];
                 }
             }
+            if (fm) atomicOr(&s_face, fm);
             pending = __syncthreads_or(has);
             if (!pending || it == inner) break;
-            int fm = 0;
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                if (!ch[r]) continue;
-                const int L = o.L[r];
-                sphi[L] = pt[r];
-                snf[L] = 1;
-#pragma unroll
-                for (int d = 0; d < 2 * ND; ++d)
-                    if (!(o.edge[r] & (1 << d))) snf[L + lds_offset<ND, TX, TY, TZ>(d)] = 1;
-                fm |= o.face[r];
-            }
-            if (fm) atomicOr(&s_face, fm);
-            __syncthreads();
 #pragma unroll
             for (int r = 0; r < S::NPT; ++r) {
                 fl[r] = false;
                 if (o.ok[r]) {
-                    fl[r] = live[r] && snf[o.L[r]];
-                    snf[o.L[r]] = 0;
+                    fl[r] = live[r] && mark[o.L[r]];
+                    mark[o.L[r]] = 0;
                 }
             }
         }
@@ -497,11 +495,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
                 push_tile(a.next, app, a.tstamp, tn, ntag);
             }
             evals += static_cast<unsigned long long>(s_evals);
+            inner_sum += static_cast<unsigned long long>(it);
         }
         __syncthreads();
     }
     app.publish(a.next);
-    if (threadIdx.x == 0 && evals) atomicAdd(&a.ctl->evals_rem, evals);
+    if (threadIdx.x == 0 && hi > lo) {
+        atomicAdd(&a.ctl->evals_rem, evals);
+        atomicAdd(&a.ctl->visits3, static_cast<unsigned long long>(hi - lo));
+        atomicAdd(&a.ctl->inner3, inner_sum);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -765,6 +768,10 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);
         st->launches = launched;
+        st->tile_visits_step2 = static_cast<int64_t>(hs.ctl->visits2);
+        st->tile_visits_step3 = static_cast<int64_t>(hs.ctl->visits3);
+        st->inner_step2 = static_cast<int64_t>(hs.ctl->inner2);
+        st->inner_step3 = static_cast<int64_t>(hs.ctl->inner3);
     }
     return rc;
 }

@@ -18,4 +18,11 @@ eik_status solve_tile(const GridDims& g, const T* F, double h, double eps,
                       const std::vector<std::pair<int, double>>& src, T* phi,
                       const eik_options& o, char* ws, hipStream_t s, eik_stats* st);
 
+size_t adjoint_workspace_bytes(const GridDims& g, const eik_options& o);
+
+template <typename T>
+eik_status adjoint_solve(const GridDims& g, const T* F, const T* phi, double h,
+                         const std::vector<std::pair<int, double>>& src, const T* dL_dphi, T* out,
+                         const eik_options& o, char* ws, hipStream_t s, eik_stats* st);
+
 }  // namespace eik

@@ -54,7 +54,7 @@ def test_options_struct_layout():
     assert ctypes.sizeof(eik.EikOptions) == 80
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
-    assert ctypes.sizeof(eik.EikStats) == 64
+    assert ctypes.sizeof(eik.EikStats) == 96
 
 
 def test_workspace_size(lib):

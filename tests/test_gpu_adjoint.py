@@ -1,0 +1,124 @@
+"""GPU parity of eik_adjoint (dL/dF at the converged solution).
+
+Against: the 1D closed form dphi_n/dF_j = -h/F_j^2; the oracle's reverse sweep
+(float64) on the oracle's own solution; the Euler identity
+sum_i F_i dL/dF_i = -L (sources valued 0); and central finite differences of
+the float64 oracle solve.  Cells where the upwind stencil differs between the
+two solutions (the loss is not differentiable there) are excluded and counted.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import helpers as H
+
+torch = pytest.importorskip("torch")
+eik = pytest.importorskip("paper_2106_15869_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_grad(P, dtype, g):
+    F = dev(P.F.astype(dtype))
+    print(f"[case] adjoint {P.name} {np.dtype(dtype).name}", flush=True)
+    phi = eik.solve(F, P.h, P.sources)
+    d = eik.adjoint(F, phi, P.h, P.sources, dev(g.astype(dtype)))
+    torch.cuda.synchronize()
+    return phi.cpu().numpy().astype(np.float64), d.cpu().numpy().astype(np.float64)
+
+
+def receiver_seed(P, k=12, seed=0):
+    r = np.random.default_rng(seed)
+    g = np.zeros(P.F.shape)
+    rec = P.receivers if P.receivers is not None else r.choice(P.F.size, size=k, replace=False)
+    g.flat[rec] = r.uniform(0.5, 2.0, size=len(rec))
+    return g
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-13), (np.float32, 2e-6)])
+def test_strip_closed_form(dtype, tol):
+    r = np.random.default_rng(5)
+    n = 300
+    F = np.exp(r.uniform(-1, 1, size=(1, n)))
+    P = W.Problem("strip", F, 0.25, np.array([40]))
+    g = np.zeros_like(F)
+    g[0, 250] = 1.0
+    _, d = gpu_grad(P, dtype, g)
+    Fq = F.astype(dtype).astype(np.float64)
+    want = np.zeros(n)
+    want[41:251] = -0.25 / Fq[0, 41:251] ** 2
+    assert np.max(np.abs(d[0] - want)) <= tol * np.max(np.abs(want))
+
+
+def _cases():
+    return [W.lognormal_2d(96, seed=3), W.random_problem(77, 2, 60), W.random_problem(78, 3, 20),
+            W.layered_3d(40, n_receivers=32), W.maze_3d(32)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("P", _cases(), ids=lambda P: P.name)
+def test_adjoint_matches_oracle(P, dtype):
+    g = receiver_seed(P)
+    phi_g, d_g = gpu_grad(P, dtype, g)
+    Fq = P.F.astype(dtype).astype(np.float64)
+    phi_o = oracle.fmm(Fq, P.h, P.sources)
+    d_o = oracle.adjoint(Fq, P.h, P.sources, phi_o, g)
+    scale = np.max(np.abs(d_o))
+    if dtype == np.float64:
+        assert np.max(np.abs(d_g - d_o)) <= 1e-9 * scale
+    else:
+        # compare where both solutions use the same upwind stencil
+        same = np.all(H.upwind_signature(phi_g) == H.upwind_signature(phi_o), axis=0)
+        err = np.abs(d_g - d_o)[same]
+        assert err.max() <= 1e-3 * scale, (err.max() / scale, int((~same).sum()))
+        # and globally the gradients agree in norm
+        assert np.linalg.norm(d_g - d_o) <= 2e-2 * np.linalg.norm(d_o)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])
+def test_euler_identity(dtype, tol):
+    P = W.layered_3d(48, n_receivers=40)
+    g = receiver_seed(P)
+    phi, d = gpu_grad(P, dtype, g)
+    L = float((g * np.where(np.isfinite(phi), phi, 0)).sum())
+    Fq = P.F.astype(dtype).astype(np.float64)
+    assert float((Fq * d).sum()) == pytest.approx(-L, rel=tol)
+
+
+def test_adjoint_against_finite_differences():
+    """Central differences of the float64 oracle solve, relative step 1e-6."""
+    P = W.layered_3d(24, dtype=np.float64, n_receivers=16)
+    g = receiver_seed(P)
+    _, d = gpu_grad(P, np.float64, g)
+    phi = oracle.fmm(P.F, P.h, P.sources)
+    r = np.random.default_rng(9)
+    cells = r.choice(np.setdiff1d(np.arange(P.F.size), P.sources), size=20, replace=False)
+    checked = 0
+    for c in cells:
+        dF = 1e-6 * P.F.flat[c]
+        Fp = P.F.copy(); Fp.flat[c] += dF
+        Fm = P.F.copy(); Fm.flat[c] -= dF
+        pp, pm = oracle.fmm(Fp, P.h, P.sources), oracle.fmm(Fm, P.h, P.sources)
+        if not np.array_equal(H.upwind_signature(pp), H.upwind_signature(pm)):
+            continue
+        fd = float(((pp - pm) * g).sum() / (2 * dF))
+        assert abs(d.flat[c] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(d).max())
+        checked += 1
+    assert checked >= 10
+
+
+def test_autograd_function():
+    P = W.lognormal_2d(80, seed=2)
+    F = dev(P.F).requires_grad_(True)
+    phi = eik.EikonalFn.apply(F, P.h, P.sources)
+    g = dev(receiver_seed(P).astype(np.float32))
+    (phi * g).sum().backward()
+    ref = eik.adjoint(F.detach(), phi.detach(), P.h, P.sources, g)
+    assert torch.equal(F.grad, ref)

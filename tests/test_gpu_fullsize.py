@@ -1,0 +1,65 @@
+"""Full-size parity: the benchmark workloads at their real sizes, solved in the
+configuration bench.py times (default options), against the float64
+fast-marching oracle on every node.  Tolerance: 1e-5 x max phi (float32),
+identical +inf masks; plus the fixed-point residual of the GPU output computed
+from the defining equation."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import helpers as H
+
+torch = pytest.importorskip("torch")
+eik = pytest.importorskip("paper_2106_15869_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _check(P, variant):
+    print(f"[case] fullsize {P.name} {variant}", flush=True)
+    F = torch.from_numpy(P.F).to(DEV)
+    phi, st = eik.solve(F, P.h, P.sources, variant=variant, stats=True)
+    got = phi.cpu().numpy().astype(np.float64)
+    print(f"[stats] {st}", flush=True)
+    ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    err = np.abs(got[fin] - ref[fin])
+    m = ref[fin].max()
+    print(f"[err] max {err.max() / m:.3e} of max phi; mean {err.mean() / m:.3e}", flush=True)
+    assert err.max() <= 1e-5 * m
+    # per-node relative error on free cells, diagnostic only
+    return got, ref
+
+
+@pytest.mark.parametrize("variant", ["tile", "node"])
+def test_maze_256(variant):
+    P = W.maze_3d(256)
+    got, _ = _check(P, variant)
+    # float32 fixed point: the equation residual is a few ulps
+    assert H.equation_residual(P.F, P.h, got, P.sources) < 1e-5
+
+
+@pytest.mark.parametrize("variant", ["tile", "node"])
+def test_lognormal_4096(variant):
+    P = W.lognormal_2d(4096)
+    _check(P, variant)
+
+
+def test_layered_192_forward_and_adjoint():
+    P = W.layered_3d(192)
+    got, ref = _check(P, "tile")
+    g = np.zeros(P.F.shape)
+    g.flat[P.receivers] = 1.0
+    F = torch.from_numpy(P.F).to(DEV)
+    phi = torch.from_numpy(got.astype(np.float32)).to(DEV)
+    d = eik.adjoint(F, phi, P.h, P.sources, torch.from_numpy(g.astype(np.float32)).to(DEV))
+    d = d.cpu().numpy().astype(np.float64)
+    do = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, ref, g)
+    assert np.linalg.norm(d - do) <= 2e-2 * np.linalg.norm(do)
+    # Euler identity on the GPU result: sum F dL/dF = -sum_r phi_r
+    L = float(got.flat[P.receivers].sum())
+    assert float((P.F.astype(np.float64) * d).sum()) == pytest.approx(-L, rel=1e-4)
