@@ -72,7 +72,20 @@ enum {
     EIK_FLAG_SKIP_REMEDY = 2u,
     /* Enqueue only: no host synchronisation, no F check, no stats.  The caller
        must pass a workspace and synchronise the stream itself. */
-    EIK_FLAG_ASYNC = 4u
+    EIK_FLAG_ASYNC = 4u,
+    /* Bracket every kernel launch with HIP events on the solve's stream and
+       report per-kind device time in eik_stats (adds host overhead). */
+    EIK_FLAG_PROFILE = 8u
+};
+
+/* Kernel kinds of eik_stats.kernel_ms / kernel_launches. */
+enum {
+    EIK_KERNEL_UPDATE = 0,  /* update-step launches */
+    EIK_KERNEL_DETECT = 1,  /* whole-grid remedy detection */
+    EIK_KERNEL_REMEDY = 2,  /* remedy-loop launches */
+    EIK_KERNEL_ADJOINT = 3, /* adjoint propagation launches */
+    EIK_KERNEL_OTHER = 4,   /* initialisation, seeding, dense adjoint passes */
+    EIK_KERNEL_KINDS = 5
 };
 
 /* Work counters of one solve (filled when eik_options.stats is non-NULL). */
@@ -89,6 +102,10 @@ typedef struct {
     int64_t tile_visits_step3;  /* tile variant: tiles processed in the remedy loop */
     int64_t inner_step2;        /* tile variant: inner iterations summed over visits */
     int64_t inner_step3;
+    int64_t written_step2;      /* node values written back to HBM in the update step */
+    int64_t written_step3;      /* ... in the remedy loop */
+    int64_t kernel_launches[EIK_KERNEL_KINDS]; /* with EIK_FLAG_PROFILE */
+    double kernel_ms[EIK_KERNEL_KINDS];        /* with EIK_FLAG_PROFILE: summed device time */
 } eik_stats;
 
 typedef struct {

@@ -41,6 +41,7 @@ EIK_VARIANT_TILE = 1
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
+EIK_FLAG_PROFILE = 8
 
 VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
             "tile": EIK_VARIANT_TILE}
@@ -51,14 +52,22 @@ EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_
            "eik_abi_version")
 
 
+KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
+
+
 class EikStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
         "remedy_initial", "max_active", "launches", "tile_visits_step2", "tile_visits_step3",
-        "inner_step2", "inner_step3")]
+        "inner_step2", "inner_step3", "written_step2", "written_step3")] + [
+        ("kernel_launches", ctypes.c_int64 * 5), ("kernel_ms", ctypes.c_double * 5)]
 
     def to_dict(self):
-        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+        d = {n: int(getattr(self, n)) for n, t in self._fields_ if t is ctypes.c_int64}
+        if any(self.kernel_launches):
+            d["kernels"] = {k: {"launches": int(self.kernel_launches[i]), "ms": float(self.kernel_ms[i])}
+                            for i, k in enumerate(KERNEL_KINDS)}
+        return d
 
 
 class EikOptions(ctypes.Structure):
@@ -137,7 +146,7 @@ def _check(rc: int):
 
 def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[Sequence[int]] = None,
                  inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
-                 skip_remedy: bool = False, async_: bool = False) -> EikOptions:
+                 skip_remedy: bool = False, async_: bool = False, profile: bool = False) -> EikOptions:
     o = EikOptions()
     _load().eik_default_options(ctypes.byref(o))
     if dtype is not None:
@@ -152,7 +161,8 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
     o.max_iters = int(max_iters)
     o.flags = ((EIK_FLAG_DETERMINISTIC if deterministic else 0) |
                (EIK_FLAG_SKIP_REMEDY if skip_remedy else 0) |
-               (EIK_FLAG_ASYNC if async_ else 0))
+               (EIK_FLAG_ASYNC if async_ else 0) |
+               (EIK_FLAG_PROFILE if profile else 0))
     return o
 
 
@@ -214,7 +224,7 @@ def _sources_array(sources, shape) -> np.ndarray:
 def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = "tile",
           source_values=None, deterministic: bool = False, skip_remedy: bool = False,
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
-          out=None, workspace=None, stats: bool = False, stream=None):
+          out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
@@ -224,7 +234,7 @@ def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = 
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy)
+                       skip_remedy, profile=profile)
     dims = _dims(F.shape)
     src = _sources_array(sources, F.shape)
     vals = None
@@ -278,14 +288,14 @@ def eik_adjoint_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] =
 
 
 def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats: bool = False,
-            stream=None):
+            stream=None, profile: bool = False):
     """dL/dF at the converged solution phi (same F, h, sources)."""
     torch = _torch()
     for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
         _check_device_tensor(t, n)
         if t.shape != F.shape or t.dtype != F.dtype:
             raise ValueError(f"{n} must match F in shape and dtype")
-    opt = make_options(_dtype_code(F))
+    opt = make_options(_dtype_code(F), profile=profile)
     s = stream if stream is not None else torch.cuda.current_stream(F.device)
     opt.stream = s.cuda_stream
     need = eik_adjoint_workspace_size(F.shape, opt)

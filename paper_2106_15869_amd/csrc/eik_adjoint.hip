@@ -312,9 +312,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, AdjGeom g, in
     app.publish(a.next);
 }
 
-__global__ void k_adj_zero(uint32_t* p, int n) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
-}
 
 struct AdjWs {
     Ctl* ctl;
@@ -388,23 +385,28 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (TX + TY + TZ);
     const int dense = static_cast<int>(std::min<int64_t>((gd.n + kBlock - 1) / kBlock, 1 << 20));
     int64_t launched = 0;
+    Profiler prof;
+    prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
 
-    HIP_TRY(launch_ctl_init(w.ctl, s));
-    hipLaunchKernelGGL((k_adj_prep<T, ND>), dim3(dense), dim3(kBlock), 0, s, gd, F, phi, static_cast<T>(h),
-                       w.up, static_cast<T*>(w.coef), static_cast<T*>(w.D), static_cast<T*>(w.lam), g);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+        hipLaunchKernelGGL((k_adj_prep<T, ND>), dim3(dense), dim3(kBlock), 0, s, gd, F, phi, static_cast<T>(h),
+                           w.up, static_cast<T*>(w.coef), static_cast<T*>(w.D), static_cast<T*>(w.lam), g);
+        return hipGetLastError();
+    }));
     for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> b{};
         b.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, src.size() - q));
         for (int j = 0; j < b.count; ++j) b.idx[j] = src[q + j].first;
-        hipLaunchKernelGGL(k_adj_mark_sources<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, b, w.up,
-                           static_cast<T*>(w.coef), static_cast<T*>(w.D));
-        HIP_TRY(hipGetLastError());
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+            hipLaunchKernelGGL(k_adj_mark_sources<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, b, w.up,
+                               static_cast<T*>(w.coef), static_cast<T*>(w.D));
+            return hipGetLastError();
+        }));
         ++launched;
     }
-    hipLaunchKernelGGL(k_adj_zero, dim3(std::min((G.ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
-                       w.tstamp, G.ntiles);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
+                  [&] { return launch_zero_words(w.tstamp, 4 * static_cast<size_t>(G.ntiles), s); }));
     AdjArgs<T> a{};
     a.F = F;
     a.phi = phi;
@@ -417,23 +419,29 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
     a.ctl = w.ctl;
     a.next = w.seg[0];
     // seeding claims with tag 1; the tag chain starts at tag[0] = 1 -> claims 2, ...
-    hipLaunchKernelGGL((k_adj_seed<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, a, G);
-    HIP_TRY(hipGetLastError());
-    launched += 3;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+        hipLaunchKernelGGL((k_adj_seed<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, a, G);
+        return hipGetLastError();
+    }));
+    launched += 4;
     auto step = [&](int64_t t) {
         AdjArgs<T> b = a;
         b.cur = w.seg[t & 1];
         b.next = w.seg[(t + 1) & 1];
         b.tag_slot = static_cast<int>(t & 1);
-        hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, b, G, inner);
-        return hipGetLastError();
+        return timed(prof, EIK_KERNEL_ADJOINT, [&] {
+            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, b, G, inner);
+            return hipGetLastError();
+        });
     };
     int64_t nl = 0;
     eik_status rc = run_loop(step, [&](int64_t t) { return w.seg[t & 1].count; }, GA, cap, async, s, &nl);
     launched += nl;
-    hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, gd.n, static_cast<const T*>(w.D),
-                       static_cast<const T*>(w.lam), out);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+        hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, gd.n, static_cast<const T*>(w.D),
+                           static_cast<const T*>(w.lam), out);
+        return hipGetLastError();
+    }));
     ++launched;
     if (async) return rc;
     HostSlots& hs = host_slots();
@@ -444,6 +452,7 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
         st->tile_visits_step3 = static_cast<int64_t>(hs.ctl->visits3);
         st->launches = launched;
+        HIP_TRY(prof.collect(st));
     }
     return rc;
 }

@@ -68,7 +68,9 @@ static eik_status check_options(const eik_options& o) {
         return fail(EIK_ERR_INVALID_ARGUMENT, "unknown variant");
     if (o.max_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "max_iters must be >= 0");
     if (o.inner_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "inner_iters must be >= 0");
-    if (o.flags & ~7u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
+    if (o.flags & ~15u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
+    if ((o.flags & EIK_FLAG_ASYNC) && (o.flags & EIK_FLAG_PROFILE))
+        return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_FLAG_PROFILE needs a synchronous call");
     if ((o.flags & EIK_FLAG_DETERMINISTIC) && o.variant != EIK_VARIANT_NODE_LIST)
         return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_FLAG_DETERMINISTIC needs the node-list variant");
     if ((o.flags & EIK_FLAG_ASYNC) && (!o.workspace || o.max_iters == 0))
@@ -86,6 +88,7 @@ static eik_status check_options(const eik_options& o) {
 // ---------------------------------------------------------------------------
 struct NodeWs {
     Ctl* ctl;
+    unsigned long long* blkstat;
     uint8_t* lab;
     uint32_t* stamp;
     SegList seg[2];
@@ -110,6 +113,7 @@ static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
     };
     const int cap = node_seg_cap(n);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kNodeSegs));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.stamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(n)));
     for (int k = 0; k < 2; ++k) {
@@ -172,9 +176,13 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * P.n + 64;
     int64_t launched = 0;
 
-    HIP_TRY(launch_ctl_init(w.ctl, s));
-    HIP_TRY(launch_init<T>(F, phi, w.lab, w.stamp, P.g.n, w.ctl, s));
-    launched += 2;
+    Profiler prof;
+    prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
+    const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * kNodeSegs;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, w.stamp, P.g.n, w.ctl, s); }));
+    launched += 3;
     // STEP 1: fixed boundary values, then their FAR neighbours become active
     std::vector<SrcBatch<T>> batches;
     for (size_t k = 0; k < src.size(); k += kMaxSrcBatch) {
@@ -186,11 +194,13 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         }
         batches.push_back(b);
     }
-    for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
-    HIP_TRY(launch_seg_clear(w.seg[0].count, kNodeSegs, s));
+    for (auto& b : batches)
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, b, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seg_clear(w.seg[0].count, kNodeSegs, s); }));
     for (size_t j = 0; j < batches.size(); ++j)
-        HIP_TRY(launch_seed_active<T>(P.g, F, w.lab, batches[j], w.seg[0],
-                                      static_cast<int>(j % kNodeSegs), s));
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+            return launch_seed_active<T>(P.g, F, w.lab, batches[j], w.seg[0], static_cast<int>(j % kNodeSegs), s);
+        }));
     launched += 1 + 2 * static_cast<int64_t>(batches.size());
 
     const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
@@ -204,6 +214,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         a.cur = w.seg[t & 1];
         a.next = w.seg[(t + 1) & 1];
         a.ctl = w.ctl;
+        a.blkstat = w.blkstat;
         a.tag_slot = static_cast<int>(t & 1);
         a.first = first ? 1 : 0;
         return a;
@@ -214,25 +225,34 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
     // STEP 2
     int64_t n2 = 0, n3 = 0;
     eik_status rc = run_loop(
-        [&](int64_t t) { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); },
+        [&](int64_t t) {
+            return timed(prof, EIK_KERNEL_UPDATE,
+                         [&] { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); });
+        },
         counts, kNodeSegs, cap, async, s, &n2);
     launched += per_iter * n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // STEP 3a: whole-grid check into list 0
-        HIP_TRY(launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.seg[0], s));
+        HIP_TRY(timed(prof, EIK_KERNEL_DETECT,
+                      [&] { return launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.seg[0], s); }));
         launched += 1;
         // STEP 3b: remedy loop
         rc = run_loop(
-            [&](int64_t t) { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); },
+            [&](int64_t t) {
+                return timed(prof, EIK_KERNEL_REMEDY,
+                             [&] { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); });
+            },
             counts, kNodeSegs, cap, async, s, &n3);
         launched += per_iter * n3;
     }
     if (async) return rc;
     HostSlots& hs = host_slots();
     HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hs.blk, w.blkstat, blk_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
     if (st) {
+        *st = eik_stats{};
         st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
         st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
@@ -241,6 +261,9 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);
         st->launches = launched;
+        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, kNodeSegs));
+        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, kNodeSegs));
+        HIP_TRY(prof.collect(st));
     }
     return rc;
 }

@@ -187,9 +187,11 @@ __device__ __forceinline__ void wave_append1(int* list, int* cnt, int item, bool
     }
 }
 
-// 64-bit counter add
-__device__ __forceinline__ void add64(unsigned long long* p, unsigned long long v) {
-    if (v) atomicAdd(p, v);
+// Add v to this workgroup's column of a per-workgroup statistics array
+// (call from one lane only).
+__device__ __forceinline__ void blk_add(unsigned long long* blkstat, int field, int nblocks,
+                                        unsigned long long v) {
+    if (v) blkstat[field * nblocks + blockIdx.x] += v;
 }
 
 }  // namespace eik

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/eik.h"
 #include "eik_internal.hpp"
@@ -33,11 +34,15 @@ struct HostSlots {
     static constexpr int kWords = 8192;  // two slots of segment lengths
     int* words = nullptr;
     Ctl* ctl = nullptr;
+    unsigned long long* blk = nullptr;   // per-workgroup statistics read-back
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ok = false;
     HostSlots() {
         if (hipHostMalloc(reinterpret_cast<void**>(&words), kWords * sizeof(int)) != hipSuccess) return;
         if (hipHostMalloc(reinterpret_cast<void**>(&ctl), sizeof(Ctl)) != hipSuccess) return;
+        if (hipHostMalloc(reinterpret_cast<void**>(&blk), sizeof(unsigned long long) * kStatFields *
+                                                              kMaxStatBlocks) != hipSuccess)
+            return;
         if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return;
         if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) return;
         ok = true;
@@ -47,6 +52,85 @@ struct HostSlots {
 inline HostSlots& host_slots() {
     static thread_local HostSlots hs;  // lives until the thread ends
     return hs;
+}
+
+// Optional per-launch device timing (EIK_FLAG_PROFILE): events bracket each
+// launch on the solve's stream; elapsed times are summed per kernel kind after
+// the final synchronisation.
+struct Profiler {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t>* pool = nullptr;
+    std::vector<int> kinds;
+    size_t used = 0;
+    hipError_t begin(int kind) {
+        if (!on) return hipSuccess;
+        hipError_t e = grow();
+        if (e != hipSuccess) return e;
+        kinds.push_back(kind);
+        return hipEventRecord((*pool)[used++], s);
+    }
+    hipError_t end() {
+        if (!on) return hipSuccess;
+        hipError_t e = grow();
+        if (e != hipSuccess) return e;
+        return hipEventRecord((*pool)[used++], s);
+    }
+    // after the stream has been synchronised
+    hipError_t collect(eik_stats* st) {
+        if (!on || !st) return hipSuccess;
+        for (int k = 0; k < EIK_KERNEL_KINDS; ++k) {
+            st->kernel_ms[k] = 0.0;
+            st->kernel_launches[k] = 0;
+        }
+        for (size_t j = 0; j + 1 < used; j += 2) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, (*pool)[j], (*pool)[j + 1]);
+            if (e != hipSuccess) return e;
+            st->kernel_ms[kinds[j / 2]] += ms;
+            st->kernel_launches[kinds[j / 2]] += 1;
+        }
+        return hipSuccess;
+    }
+    static std::vector<hipEvent_t>& thread_pool() {
+        static thread_local std::vector<hipEvent_t> p;
+        return p;
+    }
+    void start(bool enable, hipStream_t stream) {
+        on = enable;
+        s = stream;
+        pool = &thread_pool();
+        used = 0;
+        kinds.clear();
+    }
+
+   private:
+    hipError_t grow() {
+        if (used < pool->size()) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        pool->push_back(e);
+        return hipSuccess;
+    }
+};
+
+// Launch `fn` bracketed by profiler events of kind `kind`.
+template <typename Fn>
+inline hipError_t timed(Profiler& p, int kind, Fn fn) {
+    hipError_t e = p.begin(kind);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    return p.end();
+}
+
+// Sum the per-workgroup statistics columns (after the stream was synchronised
+// and `blk` copied to hs.blk).
+inline unsigned long long blk_sum(const unsigned long long* blk, int field, int nblocks) {
+    unsigned long long v = 0;
+    for (int b = 0; b < nblocks; ++b) v += blk[field * nblocks + b];
+    return v;
 }
 
 // Run `step(t)` for t = 0, 1, ... until the list a step would consume is

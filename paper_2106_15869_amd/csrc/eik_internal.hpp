@@ -20,6 +20,16 @@ struct Ctl {
     unsigned long long visits2, visits3, inner2, inner3;
 };
 
+// Per-workgroup statistics: column b of a [kStatFields][G] array is written
+// only by workgroup b of each launch (plain read-modify-write, launches are
+// ordered on the stream), so no launch serialises on a shared counter; the
+// host sums the columns after the solve.
+enum StatField {
+    SF_EVALS2 = 0, SF_EVALS3, SF_VISITS2, SF_VISITS3, SF_INNER2, SF_INNER3, SF_WRITTEN2, SF_WRITTEN3,
+    kStatFields
+};
+constexpr int kMaxStatBlocks = 1024;
+
 constexpr int kMaxSrcBatch = 64;
 
 template <typename T>
@@ -51,6 +61,7 @@ struct NodeIter {
     SegList cur;
     SegList next;
     Ctl* ctl;
+    unsigned long long* blkstat;  // [kStatFields][kNodeSegs]
     int tag_slot;      // parity of this iteration (remedy stamp tag slot)
     int first;         // first iteration of its loop
 };
@@ -78,6 +89,7 @@ hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint
 template <typename T>
 hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
 hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s);
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
                               hipStream_t s);

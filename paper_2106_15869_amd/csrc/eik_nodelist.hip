@@ -15,6 +15,8 @@
 // Lists are int32 node indices in per-workgroup segments (eik_seglist.hpp):
 // each wave compacts its items with a lane prefix sum and reserves room with
 // one LDS atomic.  Labels are bytes changed with word atomics.
+#include <algorithm>
+
 #include "eik_device.hpp"
 #include "eik_internal.hpp"
 #include "eik_seglist.hpp"
@@ -120,6 +122,10 @@ __global__ void k_seg_clear(int* count, int nseg) {
     for (int i = threadIdx.x; i < nseg; i += blockDim.x) count[i] = 0;
 }
 
+__global__ void k_zero_words(uint32_t* p, int n) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // STEP 2
 // ---------------------------------------------------------------------------
@@ -128,7 +134,7 @@ constexpr int G = kNodeSegs;
 // Shared by the in-place and the synchronous-read apply kernels.
 template <typename T, int ND>
 __device__ __forceinline__ uint32_t step2_apply_node(const NodeIter<T>& a, const Grid& g, int i,
-                                                     T pi, T pt, T eps, int (&items)[7]) {
+                                                     T pi, T pt, T eps, int (&items)[7], int& written) {
     const T inf = pos_inf<T>();
     uint32_t mask = 0;
     if (pt < inf && pi - pt <= eps) {
@@ -153,11 +159,21 @@ __device__ __forceinline__ uint32_t step2_apply_node(const NodeIter<T>& a, const
         // nothing finite upwind: not converged, back to FAR
         label_add(a.lab, i, int(L_FAR) - int(L_ACTIVE));
     } else {
-        if (pt < pi) a.phi[i] = pt;
+        if (pt < pi) {
+            a.phi[i] = pt;
+            ++written;
+        }
         items[6] = i;
         mask = 1u << 6;
     }
     return mask;
+}
+
+// Block-wide: add the lanes' counts to this workgroup's statistics column.
+__device__ __forceinline__ void flush_written(unsigned long long* blkstat, int field, int* s_w, int mine) {
+    if (mine) atomicAdd(s_w, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) blk_add(blkstat, field, G, static_cast<unsigned long long>(*s_w));
 }
 
 // Loads the list lengths, updates the per-iteration counters (block 0) and
@@ -187,9 +203,12 @@ template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T h, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
+    __shared__ int s_w;
     const Grid g = make_grid(gd);
     SegAppender app{&s_cnt};
     app.init();
+    if (threadIdx.x == 0) s_w = 0;
+    int written = 0;
     int lo, hi;
     list_prologue(a, s_pref, true, lo, hi);
     for (int base = lo; base < hi; base += kBlock) {
@@ -202,11 +221,11 @@ __global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T 
             decode<ND>(g, i, x, y, z);
             const T pi = a.phi[i];
             const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
-            mask = step2_apply_node<T, ND>(a, g, i, pi, pt, eps, items);
+            mask = step2_apply_node<T, ND>(a, g, i, pi, pt, eps, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
     }
-    __syncthreads();
+    flush_written(a.blkstat, SF_WRITTEN2, &s_w, written);
     app.publish(a.next);
 }
 
@@ -228,9 +247,12 @@ template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_step2_apply(NodeIter<T> a, GridDims gd, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
+    __shared__ int s_w;
     const Grid g = make_grid(gd);
     SegAppender app{&s_cnt};
     app.init();
+    if (threadIdx.x == 0) s_w = 0;
+    int written = 0;
     const int n = seg_prefix<G>(a.cur.count, s_pref);
     int lo, hi;
     seg_slice(n, G, lo, hi);
@@ -240,11 +262,11 @@ __global__ __launch_bounds__(kBlock) void k_step2_apply(NodeIter<T> a, GridDims 
         uint32_t mask = 0;
         if (k < hi) {
             const int i = seg_entry<G>(a.cur, s_pref, k);
-            mask = step2_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, items);
+            mask = step2_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
     }
-    __syncthreads();
+    flush_written(a.blkstat, SF_WRITTEN2, &s_w, written);
     app.publish(a.next);
 }
 
@@ -288,10 +310,11 @@ __device__ __forceinline__ bool claim(uint32_t* stamp, int q, uint32_t tag) {
 template <typename T, int ND>
 __device__ __forceinline__ uint32_t remedy_apply_node(const NodeIter<T>& a, const Grid& g, int i,
                                                       T pi, T pt, T eps, uint32_t tag,
-                                                      int (&items)[7]) {
+                                                      int (&items)[7], int& written) {
     uint32_t mask = 0;
     if (pt < pi - eps) {
         a.phi[i] = pt;
+        ++written;
         int x, y, z;
         decode<ND>(g, i, x, y, z);
         int nb[6];
@@ -324,10 +347,13 @@ template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T h, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
+    __shared__ int s_w;
     const Grid g = make_grid(gd);
     const uint32_t tag = remedy_tag(a, true);
     SegAppender app{&s_cnt};
     app.init();
+    if (threadIdx.x == 0) s_w = 0;
+    int written = 0;
     int lo, hi;
     list_prologue(a, s_pref, false, lo, hi);
     for (int base = lo; base < hi; base += kBlock) {
@@ -339,11 +365,11 @@ __global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
-            mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], pt, eps, tag, items);
+            mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], pt, eps, tag, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
     }
-    __syncthreads();
+    flush_written(a.blkstat, SF_WRITTEN3, &s_w, written);
     app.publish(a.next);
 }
 
@@ -367,10 +393,13 @@ template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_remedy_apply(NodeIter<T> a, GridDims gd, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
+    __shared__ int s_w;
     const Grid g = make_grid(gd);
     const uint32_t tag = remedy_tag(a, false);
     SegAppender app{&s_cnt};
     app.init();
+    if (threadIdx.x == 0) s_w = 0;
+    int written = 0;
     const int n = seg_prefix<G>(a.cur.count, s_pref);
     int lo, hi;
     seg_slice(n, G, lo, hi);
@@ -380,11 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_remedy_apply(NodeIter<T> a, GridDims
         uint32_t mask = 0;
         if (k < hi) {
             const int i = seg_entry<G>(a.cur, s_pref, k);
-            mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, tag, items);
+            mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], a.vals[k], eps, tag, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
     }
-    __syncthreads();
+    flush_written(a.blkstat, SF_WRITTEN3, &s_w, written);
     app.publish(a.next);
 }
 
@@ -450,6 +479,13 @@ hipError_t launch_seed_active(const GridDims& g, const T* F, uint8_t* lab, const
     else
         hipLaunchKernelGGL((k_seed_active<T, 3>), dim3(1), dim3(kMaxSrcBatch), 0, s, g, F, lab, b,
                            out, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s) {
+    const int n = static_cast<int>(bytes / 4);
+    hipLaunchKernelGGL(k_zero_words, dim3(std::min((n + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
+                       static_cast<uint32_t*>(p), n);
     return hipGetLastError();
 }
 

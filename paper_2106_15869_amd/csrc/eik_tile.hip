@@ -60,6 +60,7 @@ struct TileIter {
     SegList cur;
     SegList next;
     Ctl* ctl;
+    unsigned long long* blkstat;  // [kStatFields][GT]
     int tag_slot;
     int phase;  // 0 update step, 1 remedy loop
     int first;  // first launch of the remedy loop
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     __shared__ int s_cnt;
     __shared__ int s_face;
     __shared__ int s_evals;
+    __shared__ int s_written;
     const T inf = pos_inf<T>();
     SegAppender app{&s_cnt};
     app.init();
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     launch_stats(a, n);
     int lo, hi;
     seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0, inner_sum = 0;
+    unsigned long long evals = 0, inner_sum = 0, written = 0;
     for (int e = lo; e < hi; ++e) {
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
@@ -252,6 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         if (threadIdx.x == 0) {
             s_face = 0;
             s_evals = 0;
+            s_written = 0;
         }
         __syncthreads();
         uint8_t lab0[S::NPT];
@@ -322,15 +325,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             if (!any_active || it == inner) break;
         }
         // write back what changed
+        int my_written = 0;
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             if (!o.ok[r]) continue;
             const uint8_t st = sl[o.L[r]] & 3u;
             if (st != (lab0[r] & 3u)) a.lab[o.G[r]] = st;
             const T v = sphi[o.L[r]];
-            if (v != phi0[r]) a.phi[o.G[r]] = v;
+            if (v != phi0[r]) {
+                a.phi[o.G[r]] = v;
+                ++my_written;
+            }
         }
         if (my_evals) atomicAdd(&s_evals, my_evals);
+        if (my_written) atomicAdd(&s_written, my_written);
         __syncthreads();
         if (threadIdx.x == 0) {
             if (any_active) push_tile(a.next, app, a.tstamp, t, ntag);
@@ -339,14 +347,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
                 if (fm & (1 << d)) push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
+            written += static_cast<unsigned long long>(s_written);
         }
         __syncthreads();
     }
     app.publish(a.next);
     if (threadIdx.x == 0 && hi > lo) {
-        atomicAdd(&a.ctl->evals2, evals);
-        atomicAdd(&a.ctl->visits2, static_cast<unsigned long long>(hi - lo));
-        atomicAdd(&a.ctl->inner2, inner_sum);
+        blk_add(a.blkstat, SF_EVALS2, GT, evals);
+        blk_add(a.blkstat, SF_VISITS2, GT, static_cast<unsigned long long>(hi - lo));
+        blk_add(a.blkstat, SF_INNER2, GT, inner_sum);
+        blk_add(a.blkstat, SF_WRITTEN2, GT, written);
     }
 }
 
@@ -401,6 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     __shared__ int s_cnt;
     __shared__ int s_face;
     __shared__ int s_evals;
+    __shared__ int s_written;
     __shared__ uint32_t s_mask;
     const T inf = pos_inf<T>();
     SegAppender app{&s_cnt};
@@ -410,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     launch_stats(a, n);
     int lo, hi;
     seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0, inner_sum = 0;
+    unsigned long long evals = 0, inner_sum = 0, written = 0;
     for (int e = lo; e < hi; ++e) {
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
@@ -421,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         if (threadIdx.x == 0) {
             s_face = 0;
             s_evals = 0;
+            s_written = 0;
             s_mask = atomicExch(a.tmask + t, 0u);
         }
 #pragma unroll
@@ -474,13 +486,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
                 }
             }
         }
+        int my_written = 0;
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             if (!o.ok[r]) continue;
             const T v = sphi[o.L[r]];
-            if (v != phi0[r]) a.phi[o.G[r]] = v;
+            if (v != phi0[r]) {
+                a.phi[o.G[r]] = v;
+                ++my_written;
+            }
         }
         if (my_evals) atomicAdd(&s_evals, my_evals);
+        if (my_written) atomicAdd(&s_written, my_written);
         __syncthreads();
         if (threadIdx.x == 0) {
             if (pending) {
@@ -496,23 +513,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             }
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
+            written += static_cast<unsigned long long>(s_written);
         }
         __syncthreads();
     }
     app.publish(a.next);
     if (threadIdx.x == 0 && hi > lo) {
-        atomicAdd(&a.ctl->evals_rem, evals);
-        atomicAdd(&a.ctl->visits3, static_cast<unsigned long long>(hi - lo));
-        atomicAdd(&a.ctl->inner3, inner_sum);
+        blk_add(a.blkstat, SF_EVALS3, GT, evals);
+        blk_add(a.blkstat, SF_VISITS3, GT, static_cast<unsigned long long>(hi - lo));
+        blk_add(a.blkstat, SF_INNER3, GT, inner_sum);
+        blk_add(a.blkstat, SF_WRITTEN3, GT, written);
     }
 }
 
 // ---------------------------------------------------------------------------
 // STEP 1 helpers
 // ---------------------------------------------------------------------------
-__global__ void k_zero_u32(uint32_t* p, int n) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
-}
 
 // Initial tile list: tiles holding a grid neighbour of a source (claimed with
 // tag 1), appended to segment `seg`.
@@ -576,6 +592,7 @@ TileGeom make_geom(const GridDims& gd, const TileCfg& c) {
 
 struct TileWs {
     Ctl* ctl;
+    unsigned long long* blkstat;
     uint8_t* lab;
     uint32_t* tstamp;
     uint32_t* tmask;
@@ -596,6 +613,7 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
     };
     const int cap = 7 * ((ntiles + GT - 1) / GT) + 512;
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * GT));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
     w.tmask = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
@@ -686,14 +704,18 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
     int64_t launched = 0;
 
-    HIP_TRY(launch_ctl_init(w.ctl, s));
-    HIP_TRY(launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s));
+    Profiler prof;
+    prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
+    const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * GT;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s); }));
     // tile stamps and dirty-face masks are adjacent: clear both
-    hipLaunchKernelGGL(k_zero_u32, dim3(std::min((2 * g.ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0,
-                       s, w.tstamp, static_cast<int>(w.tmask - w.tstamp) + g.ntiles);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(launch_seg_clear(w.seg[0].count, GT, s));
-    launched += 4;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + g.ntiles), s);
+    }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seg_clear(w.seg[0].count, GT, s); }));
+    launched += 5;
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> b{};
@@ -704,17 +726,20 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         }
         batches.push_back(b);
     }
-    for (auto& b : batches) HIP_TRY(launch_seed<T>(phi, w.lab, b, s));
+    for (auto& b : batches)
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, b, s); }));
     launched += static_cast<int64_t>(batches.size());
-    if (batches.size() == 1) {
-        // tiles next to the sources (at most 6 * 64 tiles: fits one segment)
-        hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz,
-                           batches[0], w.tstamp, w.seg[0], 0);
-    } else {
-        // many sources: start from every tile; tiles with nothing to do drop out
-        hipLaunchKernelGGL(k_seed_all_tiles, dim3(GT), dim3(kBlock), 0, s, g.ntiles, w.tstamp, w.seg[0]);
-    }
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+        if (batches.size() == 1) {
+            // tiles next to the sources (at most 6 * 64 tiles: fits one segment)
+            hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz,
+                               batches[0], w.tstamp, w.seg[0], 0);
+        } else {
+            // many sources: start from every tile; tiles with nothing to do drop out
+            hipLaunchKernelGGL(k_seed_all_tiles, dim3(GT), dim3(kBlock), 0, s, g.ntiles, w.tstamp, w.seg[0]);
+        }
+        return hipGetLastError();
+    }));
     launched += 1;
 
     const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
@@ -729,6 +754,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.cur = w.seg[t & 1];
         a.next = w.seg[(t + 1) & 1];
         a.ctl = w.ctl;
+        a.blkstat = w.blkstat;
         a.tag_slot = static_cast<int>((gl + t) & 1);
         a.phase = phase;
         a.first = (phase == 1 && t == 0) ? 1 : 0;
@@ -737,8 +763,11 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     auto counts = [&](int64_t t) { return w.seg[t & 1].count; };
 
     int64_t n2 = 0;
-    eik_status rc = run_loop([&](int64_t t) { return k.update(iter_args(t, 0), g, hT, eT, inner, s); },
-                             counts, GT, cap, async, s, &n2);
+    eik_status rc = run_loop(
+        [&](int64_t t) {
+            return timed(prof, EIK_KERNEL_UPDATE, [&] { return k.update(iter_args(t, 0), g, hT, eT, inner, s); });
+        },
+        counts, GT, cap, async, s, &n2);
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
@@ -746,32 +775,41 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         TileIter<T> d = iter_args(0, 1);
         d.first = 0;
         d.next = w.seg[0];
-        HIP_TRY(k.detect(d, g, hT, eT, s));
+        HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, g, hT, eT, s); }));
         gl += 1;
         launched += 1;
         int64_t n3 = 0;
-        rc = run_loop([&](int64_t t) { return k.remedy(iter_args(t, 1), g, hT, eT, inner, s); },
-                      counts, GT, cap, async, s, &n3);
+        rc = run_loop(
+            [&](int64_t t) {
+                return timed(prof, EIK_KERNEL_REMEDY,
+                             [&] { return k.remedy(iter_args(t, 1), g, hT, eT, inner, s); });
+            },
+            counts, GT, cap, async, s, &n3);
         launched += n3;
     }
     if (async) return rc;
     HostSlots& hs = host_slots();
     HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hs.blk, w.blkstat, blk_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
     if (st) {
+        *st = eik_stats{};
         st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
-        st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
+        st->evals_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS2, GT));
         st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : gd.n - static_cast<int64_t>(src.size());
-        st->evals_remedy = static_cast<int64_t>(hs.ctl->evals_rem);
+        st->evals_remedy = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS3, GT));
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);
         st->launches = launched;
-        st->tile_visits_step2 = static_cast<int64_t>(hs.ctl->visits2);
-        st->tile_visits_step3 = static_cast<int64_t>(hs.ctl->visits3);
-        st->inner_step2 = static_cast<int64_t>(hs.ctl->inner2);
-        st->inner_step3 = static_cast<int64_t>(hs.ctl->inner3);
+        st->tile_visits_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS2, GT));
+        st->tile_visits_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS3, GT));
+        st->inner_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER2, GT));
+        st->inner_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER3, GT));
+        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, GT));
+        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, GT));
+        HIP_TRY(prof.collect(st));
     }
     return rc;
 }

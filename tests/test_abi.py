@@ -54,7 +54,7 @@ def test_options_struct_layout():
     assert ctypes.sizeof(eik.EikOptions) == 80
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
-    assert ctypes.sizeof(eik.EikStats) == 96
+    assert ctypes.sizeof(eik.EikStats) == 112 + 80
 
 
 def test_workspace_size(lib):
@@ -118,6 +118,11 @@ def test_invalid_options_rejected(lib):
     o = eik.make_options(eik.EIK_FLOAT32, "node")
     o.flags = 64
     assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node", profile=True, async_=True)
+    o.workspace = 0x100000
+    o.workspace_bytes = 1 << 30
+    o.max_iters = 10
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT  # profile needs a sync
 
 
 def test_bad_source_values_rejected(lib):
