@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: IFIM eikonal solve, 3D 256^3 float32 maze, one MI355X.
 
-One step = one complete solve (initialisation, update step, remedy step) of
-the 256^3 maze workload: blocks of 8^3 cells are obstacles (F = 0.001) with
-probability 0.3, else free (F = 1); h = 1; source at (0,0,0) with its block
-forced free.  Inputs are resident in HBM before the timed region; the
-workspace is preallocated.  value = grid nodes solved per second.
+Workload: grid 256^3, h = 1; blocks of 8^3 cells are obstacles (F = 0.001)
+with probability 0.3, else free (F = 1); source (0,0,0), its block forced
+free.  One step = one complete forward solve (initialisation, update step,
+remedy step) with the default (tile) schedule.  Inputs are resident in HBM and
+the workspace is preallocated before the timed region; value = grid nodes
+solved per second.
 
-Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs on
-a single GPU.
+Also reported: forward + adjoint (dL/dF for L = sum of phi at 64 receivers on
+the far face z = 255), the plain node-list schedule, the dominant kernel's
+achieved bandwidth against the 8 TB/s HBM peak (device time from HIP events
+on the library's stream, bytes from the algorithmic count below), and the
+float64 fast-marching oracle on the host as a CPU baseline.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 
 from __future__ import annotations
@@ -16,7 +22,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -37,25 +42,48 @@ def parse():
     ap.add_argument("--variant", default="tile", choices=["tile", "node"])
     ap.add_argument("--n", type=int, default=256, help="grid side of the 3D maze")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the secondary variant timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip adjoint and node-list timings")
     return ap.parse_args()
 
 
-def time_solves(eik, torch, F, P, variant, steps, warmup, phi, ws, stream):
+def algorithmic_bytes(kind, st, variant, n_nodes, tile_nodes, esz=4):
+    """Bytes the method must move for one kernel kind over a whole solve.
+
+    unit of work (tile schedule): one tile visit reads each node's F and phi
+    (2*esz) and its label (1 B) once into LDS; every value that changes is
+    written back (esz, plus 1 B label in the update step).
+    unit of work (node list): one evaluation reads the node's F and phi (2*esz)
+    plus about 9 B of list and label traffic; changed values are written.
+    detection: every node's F, phi and label once.
+    """
+    if kind == "detect":
+        return n_nodes * (2 * esz + 1)
+    if variant == "tile":
+        if kind == "update":
+            return st["tile_visits_step2"] * tile_nodes * (2 * esz + 1) + st["written_step2"] * (esz + 1)
+        if kind == "remedy":
+            return st["tile_visits_step3"] * tile_nodes * (2 * esz + 1) + st["written_step3"] * esz
+    else:
+        if kind == "update":
+            return st["evals_step2"] * (2 * esz + 9) + st["written_step2"] * esz
+        if kind == "remedy":
+            return st["evals_remedy"] * (2 * esz + 9) + st["written_step3"] * esz
+    return None
+
+
+def timed(torch, fn, steps, warmup, stream):
     for _ in range(warmup):
-        eik.solve(F, P.h, P.sources, variant=variant, out=phi, workspace=ws, stream=stream)
+        fn()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
-        eik.solve(F, P.h, P.sources, variant=variant, out=phi, workspace=ws, stream=stream)
+        fn()
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
-    ms = e0.elapsed_time(e1) / steps
-    return ms, wall
+    return e0.elapsed_time(e1) / steps, (time.perf_counter() - t0) * 1e3 / steps
 
 
 def cpu_baseline(P):
@@ -65,15 +93,15 @@ def cpu_baseline(P):
     oracle.fmm(F64, P.h, P.sources)
     dt = time.perf_counter() - t0
     return {"value": P.n / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full {P.name} solve by the float64 fast-marching oracle "
-                      f"(single thread, {dt:.1f} s)"}
+            "sample": f"one full {P.name} solve (16.8M nodes) by the float64 heap-ordered "
+                      f"fast-marching oracle, single thread: {dt:.1f} s"}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "the multi-GPU design is described but not built", file=sys.stderr)
+              "the multi-GPU design is described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2106_15869_amd as eik
@@ -85,27 +113,41 @@ def main():
     F = torch.from_numpy(P.F).to(dev)
     phi = torch.empty_like(F)
     stream = torch.cuda.current_stream(dev)
-    need = max(eik.eik_workspace_size(P.dims, eik.make_options(eik.EIK_FLOAT32, v))
-               for v in ("tile", "node"))
+    need = max(eik.eik_workspace_size(P.dims, eik.make_options(eik.EIK_FLOAT32, v)) for v in ("tile", "node"))
+    need = max(need, eik.eik_adjoint_workspace_size(P.dims, eik.make_options(eik.EIK_FLOAT32)))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
-    # one solve for the work counters
-    _, st = eik.solve(F, P.h, P.sources, variant=a.variant, out=phi, workspace=ws, stats=True)
-    ms, wall = time_solves(eik, torch, F, P, a.variant, a.steps, a.warmup, phi, ws, stream)
+    def fwd(variant=a.variant, **kw):
+        return eik.solve(F, P.h, P.sources, variant=variant, out=phi, workspace=ws, stream=stream, **kw)
+
+    # counters of one solve, then the timed region
+    _, st = fwd(stats=True)
+    ms, wall = timed(torch, fwd, a.steps, a.warmup, stream)
     value = P.n / (ms / 1e3)
 
-    extra = {}
-    if not a.no_extra:
-        other = "node" if a.variant == "tile" else "tile"
-        try:
-            _, st_o = eik.solve(F, P.h, P.sources, variant=other, out=phi, workspace=ws, stats=True)
-            ms_o, _ = time_solves(eik, torch, F, P, other, max(1, a.steps // 2), 1, phi, ws, stream)
-            extra[other] = {"ms_per_solve": ms_o, "node_updates_per_s": P.n / (ms_o / 1e3),
-                            "stats": st_o}
-        except Exception as e:  # report, never hide
-            extra[other] = {"error": str(e)}
+    # dominant kernel, timed with HIP events on the library's stream
+    _, pst = fwd(stats=True, profile=True)
+    kernels = pst["kernels"]
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    tile_nodes = 8 * 8 * 8
+    bytes_dom = algorithmic_bytes(dom, pst, a.variant, P.n, tile_nodes)
+    dom_ms = kernels[dom]["ms"]
+    dom_launches = kernels[dom]["launches"]
+    achieved = bytes_dom / (dom_ms / 1e3) / 1e9 if bytes_dom else None
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"{'k_tile_' if a.variant == 'tile' else 'k_'}{dom}",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+        "traffic": None,
+        "launches": dom_launches,
+        "avg_launch_us": dom_ms * 1e3 / max(dom_launches, 1),
+        "algorithmic_bytes_per_launch": bytes_dom / max(dom_launches, 1) if bytes_dom else None,
+        "kernel_ms_per_solve": {k: v["ms"] for k, v in kernels.items()},
+    }
 
-    evals = st["evals_step2"] + st["evals_detect"] + st["evals_remedy"]
     out = {
         "metric": "node-updates/s and solve ms, 3D 256^3 FP32, fwd and fwd+adjoint; % HBM peak",
         "value": value,
@@ -119,14 +161,34 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"maze_3d_{a.n}^3 (8^3 obstacle blocks F=0.001 p=0.3, F=1 else; "
-                               "h=1; source (0,0,0)); forward solve",
-                   "variant": a.variant, "grid": list(P.dims), "nodes": P.n},
+        "config": {"workload": f"maze_3d {a.n}^3: 8^3 obstacle blocks (F=0.001, p=0.3) in F=1, h=1, "
+                               "source (0,0,0); forward solve",
+                   "schedule": a.variant, "grid": list(P.dims), "nodes": P.n},
+        "roofline": roofline,
         "wall_ms_per_step": wall,
-        "evaluations_per_s": evals / (ms / 1e3),
+        "evaluations_per_s": (st["evals_step2"] + st["evals_detect"] + st["evals_remedy"]) / (ms / 1e3),
         "stats": st,
-        "other_variants": extra,
     }
+
+    if not a.no_extra:
+        rec = W.receivers_on_face(P.dims, 64, W.BASE_SEED + 1, axis=0, side=-1)
+        g = torch.zeros_like(F)
+        g.view(-1)[torch.from_numpy(rec).to(dev)] = 1.0
+        dF = torch.empty_like(F)
+
+        def fwd_adj():
+            fwd()
+            eik.adjoint(F, phi, P.h, P.sources, g, out=dF, workspace=ws, stream=stream)
+
+        ms_fa, _ = timed(torch, fwd_adj, max(1, a.steps // 2), 1, stream)
+        out["fwd_adjoint"] = {"ms_per_step": ms_fa, "node_updates_per_s": P.n / (ms_fa / 1e3),
+                              "adjoint_ms": ms_fa - ms,
+                              "loss": "sum of phi at 64 receivers on the face z = 255"}
+        other = "node" if a.variant == "tile" else "tile"
+        _, st_o = fwd(variant=other, stats=True)
+        ms_o, _ = timed(torch, lambda: fwd(variant=other), max(1, a.steps // 2), 1, stream)
+        out["other_schedule"] = {"schedule": other, "ms_per_step": ms_o,
+                                 "node_updates_per_s": P.n / (ms_o / 1e3), "stats": st_o}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

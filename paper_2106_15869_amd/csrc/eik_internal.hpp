@@ -28,7 +28,7 @@ enum StatField {
     SF_EVALS2 = 0, SF_EVALS3, SF_VISITS2, SF_VISITS3, SF_INNER2, SF_INNER3, SF_WRITTEN2, SF_WRITTEN3,
     kStatFields
 };
-constexpr int kMaxStatBlocks = 1024;
+constexpr int kMaxStatBlocks = 2048;
 
 constexpr int kMaxSrcBatch = 64;
 

@@ -40,7 +40,10 @@ namespace {
 // LDS label byte: bits 0-1 state, bit 2 passable (F > 0), bit 3 outside grid.
 constexpr uint8_t kPass = 4u, kOut = 8u;
 // Workgroups per tile launch (one list segment each).
-constexpr int GT = 1024;
+#ifndef EIK_TILE_SEGS
+#define EIK_TILE_SEGS 1024
+#endif
+constexpr int GT = EIK_TILE_SEGS;
 // Dirty-face mask bit meaning "recheck every node of the tile".
 constexpr uint32_t kAllFaces = 64u;
 
@@ -67,7 +70,6 @@ struct TileIter {
 };
 
 __device__ __forceinline__ bool claim_tile(uint32_t* tstamp, int t, uint32_t tag) {
-    if (__hip_atomic_load(tstamp + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tag) return false;
     return atomicMax(tstamp + t, tag) < tag;
 }
 
@@ -97,24 +99,33 @@ struct Owned {
 };
 
 // Stage the tile and its halo: values (+inf outside) and labels (kOut outside).
+// All global loads of a lane are issued before its first LDS store.
 template <typename T, int ND, int TX, int TY, int TZ>
 __device__ __forceinline__ void stage(const TileGeom& g, int x0, int y0, int z0, const T* phi,
                                       const uint8_t* lab, T* sphi, uint8_t* sl) {
     using S = Shape<ND, TX, TY, TZ>;
+    constexpr int NIT = (S::NL + kBlock - 1) / kBlock;
     const T inf = pos_inf<T>();
-    for (int q = threadIdx.x; q < S::NL; q += kBlock) {
+    T v[NIT];
+    uint8_t l[NIT];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int q = threadIdx.x + j * kBlock;
         const int lx = q % S::LX;
         const int ly = (q / S::LX) % S::LY;
         const int lz = q / (S::LX * S::LY);
         const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
-        const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-        if (in) {
-            const int G = (gz * g.ny + gy) * g.nx + gx;
-            sphi[q] = phi[G];
-            sl[q] = lab[G];
-        } else {
-            sphi[q] = inf;
-            sl[q] = kOut;
+        const bool in = q < S::NL && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+        const int G = (gz * g.ny + gy) * g.nx + gx;
+        v[j] = in ? phi[G] : inf;
+        l[j] = in ? lab[G] : kOut;
+    }
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int q = threadIdx.x + j * kBlock;
+        if (q < S::NL) {
+            sphi[q] = v[j];
+            sl[q] = l[j];
         }
     }
 }
@@ -340,11 +351,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         if (my_evals) atomicAdd(&s_evals, my_evals);
         if (my_written) atomicAdd(&s_written, my_written);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (any_active) push_tile(a.next, app, a.tstamp, t, ntag);
+        // scheduling: lane d < 2*ND handles face d, lane 6 the tile itself,
+        // so the device atomics of one visit are in flight together
+        if (threadIdx.x < 7) {
+            const int d = threadIdx.x;
             const int fm = s_face;
-            for (int d = 0; d < 2 * ND; ++d)
-                if (fm & (1 << d)) push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
+            if (d == 6) {
+                if (any_active) push_tile(a.next, app, a.tstamp, t, ntag);
+            } else if (d < 2 * ND && (fm & (1 << d))) {
+                push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
+            }
+        }
+        if (threadIdx.x == 0) {
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
             written += static_cast<unsigned long long>(s_written);
@@ -426,6 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        uint32_t mask_in = 0;
+        if (threadIdx.x == 0) mask_in = atomicExch(a.tmask + t, 0u);  // in flight during staging
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         Owned<T, S::NPT> o;
         own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
@@ -433,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             s_face = 0;
             s_evals = 0;
             s_written = 0;
-            s_mask = atomicExch(a.tmask + t, 0u);
+            s_mask = mask_in;
         }
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r)
@@ -499,18 +519,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         if (my_evals) atomicAdd(&s_evals, my_evals);
         if (my_written) atomicAdd(&s_written, my_written);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (pending) {
-                atomicOr(a.tmask + t, kAllFaces);
-                push_tile(a.next, app, a.tstamp, t, ntag);
-            }
+        // scheduling, one lane per target tile (see the update kernel)
+        if (threadIdx.x < 7) {
+            const int d = threadIdx.x;
             const int fm = s_face;
-            for (int d = 0; d < 2 * ND; ++d) {
-                if (!(fm & (1 << d))) continue;
+            if (d == 6) {
+                if (pending) {
+                    atomicOr(a.tmask + t, kAllFaces);
+                    push_tile(a.next, app, a.tstamp, t, ntag);
+                }
+            } else if (d < 2 * ND && (fm & (1 << d))) {
                 const int tn = neighbour_tile(g, t, d);
                 atomicOr(a.tmask + tn, 1u << (d ^ 1));  // the face of tn shared with t
                 push_tile(a.next, app, a.tstamp, tn, ntag);
             }
+        }
+        if (threadIdx.x == 0) {
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
             written += static_cast<unsigned long long>(s_written);

@@ -42,7 +42,9 @@ def receiver_seed(P, k=12, seed=0):
     return g
 
 
-@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-13), (np.float32, 2e-6)])
+# float32: the weights come from differences of neighbouring phi values (up to
+# ~50 here), so their relative error is about ulp(50) / (h/F) ~ 1e-5.
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-13), (np.float32, 1e-4)])
 def test_strip_closed_form(dtype, tol):
     r = np.random.default_rng(5)
     n = 300
