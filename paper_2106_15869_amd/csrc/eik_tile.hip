@@ -41,7 +41,7 @@ namespace {
 constexpr uint8_t kPass = 4u, kOut = 8u;
 // Workgroups per tile launch (one list segment each).
 #ifndef EIK_TILE_SEGS
-#define EIK_TILE_SEGS 1024
+#define EIK_TILE_SEGS 2048
 #endif
 constexpr int GT = EIK_TILE_SEGS;
 // Dirty-face mask bit meaning "recheck every node of the tile".
@@ -252,10 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     const uint32_t ntag = launch_tag(a);
     const int n = seg_prefix<GT>(a.cur.count, s_pref);
     launch_stats(a, n);
-    int lo, hi;
-    seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0, inner_sum = 0, written = 0;
-    for (int e = lo; e < hi; ++e) {
+    // strided assignment: neighbouring list entries (often tiles scheduled by
+    // the same tile, with similar work) go to different workgroups
+    unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
+    for (int e = blockIdx.x; e < n; e += GT) {
+        ++visits;
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
@@ -370,9 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         __syncthreads();
     }
     app.publish(a.next);
-    if (threadIdx.x == 0 && hi > lo) {
+    if (threadIdx.x == 0 && visits) {
         blk_add(a.blkstat, SF_EVALS2, GT, evals);
-        blk_add(a.blkstat, SF_VISITS2, GT, static_cast<unsigned long long>(hi - lo));
+        blk_add(a.blkstat, SF_VISITS2, GT, visits);
         blk_add(a.blkstat, SF_INNER2, GT, inner_sum);
         blk_add(a.blkstat, SF_WRITTEN2, GT, written);
     }
@@ -437,10 +438,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     const uint32_t ntag = launch_tag(a);
     const int n = seg_prefix<GT>(a.cur.count, s_pref);
     launch_stats(a, n);
-    int lo, hi;
-    seg_slice(n, GT, lo, hi);
-    unsigned long long evals = 0, inner_sum = 0, written = 0;
-    for (int e = lo; e < hi; ++e) {
+    // strided assignment: neighbouring list entries (often tiles scheduled by
+    // the same tile, with similar work) go to different workgroups
+    unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
+    for (int e = blockIdx.x; e < n; e += GT) {
+        ++visits;
         const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
@@ -542,9 +544,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         __syncthreads();
     }
     app.publish(a.next);
-    if (threadIdx.x == 0 && hi > lo) {
+    if (threadIdx.x == 0 && visits) {
         blk_add(a.blkstat, SF_EVALS3, GT, evals);
-        blk_add(a.blkstat, SF_VISITS3, GT, static_cast<unsigned long long>(hi - lo));
+        blk_add(a.blkstat, SF_VISITS3, GT, visits);
         blk_add(a.blkstat, SF_INNER3, GT, inner_sum);
         blk_add(a.blkstat, SF_WRITTEN3, GT, written);
     }
