@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid side of the 3D maze")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip adjoint and node-list timings")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -104,6 +106,15 @@ def main():
               "the multi-GPU design is described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_calibration:
+        n = a.copy_calibration << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n}), flush=True)
+        return
     import paper_2106_15869_amd as eik
     import workloads as W
 
