@@ -73,6 +73,24 @@ def algorithmic_bytes(kind, st, variant, n_nodes, tile_nodes, esz=4):
     return None
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel source; else None."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic_json:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel") != kernel:
+                continue
+            src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+            if hashlib.sha256(src).hexdigest()[:16] == rec["sha256_16"]:
+                return rec["bytes_per_launch"]
+    return None
+
+
 def timed(torch, fn, steps, warmup, stream):
     for _ in range(warmup):
         fn()
@@ -152,7 +170,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS if achieved else None,
-        "traffic": None,
+        "traffic": measured_traffic(f"{'k_tile_' if a.variant == 'tile' else 'k_'}{dom}"),
         "launches": dom_launches,
         "avg_launch_us": dom_ms * 1e3 / max(dom_launches, 1),
         "algorithmic_bytes_per_launch": bytes_dom / max(dom_launches, 1) if bytes_dom else None,
