@@ -40,10 +40,11 @@ namespace {
 // LDS label byte: bits 0-1 state, bit 2 passable (F > 0), bit 3 outside grid.
 constexpr uint8_t kPass = 4u, kOut = 8u;
 // Workgroups per tile launch (one list segment each).
-#ifndef EIK_TILE_SEGS
-#define EIK_TILE_SEGS 2048
-#endif
-constexpr int GT = EIK_TILE_SEGS;
+// Persistent workgroups per tile launch; group k = blockIdx % kSub drains
+// sub-list k of the launch's tile list.
+constexpr int GT = 2048;
+constexpr int kSub = 8;       // sub-lists per tile list
+constexpr int kPad = 32;      // ints between counters (separate cache lines)
 // Dirty-face mask bit meaning "recheck every node of the tile".
 constexpr uint32_t kAllFaces = 64u;
 
@@ -53,6 +54,16 @@ struct TileGeom {
     int ntiles;
 };
 
+// A tile list: kSub sub-lists of `cap` tile ids.  count[k * kPad] is the
+// length of sub-list k (appended with atomicAdd by producers), fetch[k * kPad]
+// the next entry a consumer of sub-list k takes (atomicAdd by consumers).
+struct TList {
+    int* data;
+    int* count;
+    int* fetch;
+    int cap;
+};
+
 template <typename T>
 struct TileIter {
     const T* F;
@@ -60,10 +71,12 @@ struct TileIter {
     uint8_t* lab;
     uint32_t* tstamp;
     uint32_t* tmask;   // per tile: dirty faces (bit d) or kAllFaces
-    SegList cur;
-    SegList next;
+    TList cur;
+    TList next;
+    int* zero_count;   // counters of the list two launches ahead: cleared by this launch
+    int* zero_fetch;
     Ctl* ctl;
-    unsigned long long* blkstat;  // [kStatFields][GT]
+    unsigned long long* blkstat;  // [kStatFields][kMaxStatBlocks], column blockIdx % kMaxStatBlocks
     int tag_slot;
     int phase;  // 0 update step, 1 remedy loop
     int first;  // first launch of the remedy loop
@@ -227,9 +240,45 @@ __device__ __forceinline__ void launch_stats(const TileIter<T>& a, int n) {
     }
 }
 
-__device__ __forceinline__ void push_tile(const SegList& out, SegAppender& app, uint32_t* tstamp, int t,
-                                          uint32_t tag) {
-    if (claim_tile(tstamp, t, tag)) app.push_one(out, t);
+// Claim tile t for the next list and append it to sub-list t % kSub.
+__device__ __forceinline__ void push_tile(const TList& out, uint32_t* tstamp, int t, uint32_t tag) {
+    if (!claim_tile(tstamp, t, tag)) return;
+    const int k = t & (kSub - 1);
+    const int pos = atomicAdd(out.count + k * kPad, 1);
+    out.data[static_cast<size_t>(k) * out.cap + pos] = t;
+}
+
+// Clear the counters of the list two launches ahead (nobody reads or writes
+// them during this launch) and return the total length of the current list.
+template <typename T>
+__device__ __forceinline__ int list_open(const TileIter<T>& a, int* s_len) {
+    if (blockIdx.x == 0 && threadIdx.x < kSub) {
+        a.zero_count[threadIdx.x * kPad] = 0;
+        a.zero_fetch[threadIdx.x * kPad] = 0;
+    }
+    if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
+    __syncthreads();
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) n += s_len[k];
+    return n;
+}
+
+// Next entry of sub-list k for this workgroup (-1 when drained).  Lane 0
+// fetches; the value is broadcast through LDS.
+__device__ __forceinline__ int list_fetch(const TList& L, int k, int len, int* s_slot) {
+    if (threadIdx.x == 0) {
+        const int e = atomicAdd(L.fetch + k * kPad, 1);
+        *s_slot = e < len ? L.data[static_cast<size_t>(k) * L.cap + e] : -1;
+    }
+    __syncthreads();
+    const int t = *s_slot;
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ void stat_add(unsigned long long* blkstat, int field, unsigned long long v) {
+    if (v) atomicAdd(blkstat + field * kMaxStatBlocks + (blockIdx.x & (kMaxStatBlocks - 1)), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,23 +290,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
-    __shared__ int s_pref[GT + 1];
-    __shared__ int s_cnt;
+    __shared__ int s_len[kSub];
+    __shared__ int s_slot;
     __shared__ int s_face;
     __shared__ int s_evals;
     __shared__ int s_written;
     const T inf = pos_inf<T>();
-    SegAppender app{&s_cnt};
-    app.init();
     const uint32_t ntag = launch_tag(a);
-    const int n = seg_prefix<GT>(a.cur.count, s_pref);
+    const int n = list_open(a, s_len);
     launch_stats(a, n);
-    // strided assignment: neighbouring list entries (often tiles scheduled by
-    // the same tile, with similar work) go to different workgroups
+    // workgroups of group k take entries of sub-list k one at a time
+    const int k = blockIdx.x & (kSub - 1);
+    const int len = s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
-    for (int e = blockIdx.x; e < n; e += GT) {
+    for (;;) {
+        const int t = list_fetch(a.cur, k, len, &s_slot);
+        if (t < 0) break;
         ++visits;
-        const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
@@ -358,9 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             const int d = threadIdx.x;
             const int fm = s_face;
             if (d == 6) {
-                if (any_active) push_tile(a.next, app, a.tstamp, t, ntag);
+                if (any_active) push_tile(a.next, a.tstamp, t, ntag);
             } else if (d < 2 * ND && (fm & (1 << d))) {
-                push_tile(a.next, app, a.tstamp, neighbour_tile(g, t, d), ntag);
+                push_tile(a.next, a.tstamp, neighbour_tile(g, t, d), ntag);
             }
         }
         if (threadIdx.x == 0) {
@@ -370,12 +419,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         }
         __syncthreads();
     }
-    app.publish(a.next);
     if (threadIdx.x == 0 && visits) {
-        blk_add(a.blkstat, SF_EVALS2, GT, evals);
-        blk_add(a.blkstat, SF_VISITS2, GT, visits);
-        blk_add(a.blkstat, SF_INNER2, GT, inner_sum);
-        blk_add(a.blkstat, SF_WRITTEN2, GT, written);
+        stat_add(a.blkstat, SF_EVALS2, evals);
+        stat_add(a.blkstat, SF_VISITS2, visits);
+        stat_add(a.blkstat, SF_INNER2, inner_sum);
+        stat_add(a.blkstat, SF_WRITTEN2, written);
     }
 }
 
@@ -387,13 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
-    __shared__ int s_cnt;
-    SegAppender app{&s_cnt};
-    app.init();
     const uint32_t ntag = launch_tag(a);
-    int lo, hi;
-    seg_slice(g.ntiles, GT, lo, hi);
-    for (int t = lo; t < hi; ++t) {
+    for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
@@ -409,11 +452,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
         }
         if (__syncthreads_or(flag) && threadIdx.x == 0) {
             atomicOr(a.tmask + t, kAllFaces);
-            push_tile(a.next, app, a.tstamp, t, ntag);
+            push_tile(a.next, a.tstamp, t, ntag);
         }
     }
-    __syncthreads();
-    app.publish(a.next);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,24 +467,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
     __shared__ uint8_t snf[2][S::NL];  // flags for the next inner iteration (double buffered)
-    __shared__ int s_pref[GT + 1];
-    __shared__ int s_cnt;
+    __shared__ int s_len[kSub];
+    __shared__ int s_slot;
     __shared__ int s_face;
     __shared__ int s_evals;
     __shared__ int s_written;
     __shared__ uint32_t s_mask;
     const T inf = pos_inf<T>();
-    SegAppender app{&s_cnt};
-    app.init();
     const uint32_t ntag = launch_tag(a);
-    const int n = seg_prefix<GT>(a.cur.count, s_pref);
+    const int n = list_open(a, s_len);
     launch_stats(a, n);
-    // strided assignment: neighbouring list entries (often tiles scheduled by
-    // the same tile, with similar work) go to different workgroups
+    const int k = blockIdx.x & (kSub - 1);
+    const int len = s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
-    for (int e = blockIdx.x; e < n; e += GT) {
+    for (;;) {
+        const int t = list_fetch(a.cur, k, len, &s_slot);
+        if (t < 0) break;
         ++visits;
-        const int t = seg_entry<GT>(a.cur, s_pref, e);
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         uint32_t mask_in = 0;
@@ -528,12 +568,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             if (d == 6) {
                 if (pending) {
                     atomicOr(a.tmask + t, kAllFaces);
-                    push_tile(a.next, app, a.tstamp, t, ntag);
+                    push_tile(a.next, a.tstamp, t, ntag);
                 }
             } else if (d < 2 * ND && (fm & (1 << d))) {
                 const int tn = neighbour_tile(g, t, d);
                 atomicOr(a.tmask + tn, 1u << (d ^ 1));  // the face of tn shared with t
-                push_tile(a.next, app, a.tstamp, tn, ntag);
+                push_tile(a.next, a.tstamp, tn, ntag);
             }
         }
         if (threadIdx.x == 0) {
@@ -543,12 +583,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         }
         __syncthreads();
     }
-    app.publish(a.next);
     if (threadIdx.x == 0 && visits) {
-        blk_add(a.blkstat, SF_EVALS3, GT, evals);
-        blk_add(a.blkstat, SF_VISITS3, GT, visits);
-        blk_add(a.blkstat, SF_INNER3, GT, inner_sum);
-        blk_add(a.blkstat, SF_WRITTEN3, GT, written);
+        stat_add(a.blkstat, SF_EVALS3, evals);
+        stat_add(a.blkstat, SF_VISITS3, visits);
+        stat_add(a.blkstat, SF_INNER3, inner_sum);
+        stat_add(a.blkstat, SF_WRITTEN3, written);
     }
 }
 
@@ -557,10 +596,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
 // ---------------------------------------------------------------------------
 
 // Initial tile list: tiles holding a grid neighbour of a source (claimed with
-// tag 1), appended to segment `seg`.
+// tag 1).
 template <typename T>
 __global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcBatch<T> b,
-                             uint32_t* tstamp, SegList out, int seg) {
+                             uint32_t* tstamp, TList out) {
     const int k = threadIdx.x;
     if (k >= b.count) return;
     const int i = b.idx[k];
@@ -569,21 +608,19 @@ __global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcB
     for (int d = 0; d < 2 * nd; ++d) {
         const int X = x + dx[d], Y = y + dy[d], Z = z + dz[d];
         if (X < 0 || X >= g.nx || Y < 0 || Y >= g.ny || Z < 0 || Z >= g.nz) continue;
-        const int t = ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_);
-        if (claim_tile(tstamp, t, 1u)) out.data[static_cast<size_t>(seg) * out.cap + atomicAdd(out.count + seg, 1)] = t;
+        push_tile(out, tstamp, ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_), 1u);
     }
 }
 
 // Initial tile list holding every tile (used when there are many sources):
-// workgroup b lists its contiguous slice of tiles in its own segment.
-__global__ void k_seed_all_tiles(int ntiles, uint32_t* tstamp, SegList out) {
-    int lo, hi;
-    seg_slice(ntiles, GT, lo, hi);
-    for (int t = lo + static_cast<int>(threadIdx.x); t < hi; t += kBlock) {
+// tile t is entry t / kSub of sub-list t % kSub.
+__global__ void k_seed_all_tiles(int ntiles, uint32_t* tstamp, TList out) {
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += gridDim.x * kBlock) {
         tstamp[t] = 1u;
-        out.data[static_cast<size_t>(blockIdx.x) * out.cap + (t - lo)] = t;
+        out.data[static_cast<size_t>(t & (kSub - 1)) * out.cap + (t / kSub)] = t;
     }
-    if (threadIdx.x == 0) out.count[blockIdx.x] = hi - lo;
+    if (blockIdx.x == 0 && threadIdx.x < kSub)
+        out.count[threadIdx.x * kPad] = (ntiles - static_cast<int>(threadIdx.x) + kSub - 1) / kSub;
 }
 
 // ---------------------------------------------------------------------------
@@ -622,13 +659,17 @@ struct TileWs {
     uint8_t* lab;
     uint32_t* tstamp;
     uint32_t* tmask;
-    SegList seg[2];
+    int* data[2];       // two list buffers (alternating)
+    int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}
+    int cap;
     size_t bytes;
+    int* count_of(int set) const { return counters + set * 2 * kSub * kPad; }
+    int* fetch_of(int set) const { return counters + set * 2 * kSub * kPad + kSub * kPad; }
 };
 
-// A segment holds what one workgroup can schedule from its slice of at most
-// ceil(ntiles / GT) tiles (itself and six face neighbours each), plus room for
-// source seeding.
+constexpr size_t kCounterBytes = 3 * 2 * kSub * kPad * sizeof(int);
+
+// A sub-list can receive every tile (tiles are deduplicated per list).
 TileWs tile_layout(char* base, int64_t n, int ntiles) {
     TileWs w{};
     size_t off = 0;
@@ -637,17 +678,14 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
         off = align_up(off + b, 256);
         return p;
     };
-    const int cap = 7 * ((ntiles + GT - 1) / GT) + 512;
+    w.cap = ntiles + 64;
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
-    w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * GT));
+    w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
     w.tmask = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
-    for (int k = 0; k < 2; ++k) {
-        w.seg[k].cap = cap;
-        w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(GT)));
-        w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * GT));
-    }
+    w.counters = reinterpret_cast<int*>(take(kCounterBytes));
+    for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
     w.bytes = off;
     return w;
 }
@@ -732,7 +770,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
 
     Profiler prof;
     prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
-    const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * GT;
+    const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks;
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s); }));
@@ -740,7 +778,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
         return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + g.ntiles), s);
     }));
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seg_clear(w.seg[0].count, GT, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
     launched += 5;
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
@@ -755,14 +793,23 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     for (auto& b : batches)
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, b, s); }));
     launched += static_cast<int64_t>(batches.size());
+    auto list_of = [&](int64_t t) {
+        TList L;
+        L.data = w.data[t & 1];
+        L.count = w.count_of(static_cast<int>(t % 3));
+        L.fetch = w.fetch_of(static_cast<int>(t % 3));
+        L.cap = w.cap;
+        return L;
+    };
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
         if (batches.size() == 1) {
-            // tiles next to the sources (at most 6 * 64 tiles: fits one segment)
+            // tiles next to the sources
             hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz,
-                               batches[0], w.tstamp, w.seg[0], 0);
+                               batches[0], w.tstamp, list_of(0));
         } else {
             // many sources: start from every tile; tiles with nothing to do drop out
-            hipLaunchKernelGGL(k_seed_all_tiles, dim3(GT), dim3(kBlock), 0, s, g.ntiles, w.tstamp, w.seg[0]);
+            hipLaunchKernelGGL(k_seed_all_tiles, dim3(std::min((g.ntiles + kBlock - 1) / kBlock, 1024)),
+                               dim3(kBlock), 0, s, g.ntiles, w.tstamp, list_of(0));
         }
         return hipGetLastError();
     }));
@@ -770,6 +817,8 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
 
     const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
     int64_t gl = 0;  // launches in the tag chain so far (selects the tag slot)
+    // launch t drains list t and fills list t + 1; lists alternate two buffers
+    // and three counter sets (the set of list t + 2 is cleared by launch t)
     auto iter_args = [&](int64_t t, int phase) {
         TileIter<T> a{};
         a.F = F;
@@ -777,8 +826,10 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.lab = w.lab;
         a.tstamp = w.tstamp;
         a.tmask = w.tmask;
-        a.cur = w.seg[t & 1];
-        a.next = w.seg[(t + 1) & 1];
+        a.cur = list_of(t);
+        a.next = list_of(t + 1);
+        a.zero_count = w.count_of(static_cast<int>((t + 2) % 3));
+        a.zero_fetch = w.fetch_of(static_cast<int>((t + 2) % 3));
         a.ctl = w.ctl;
         a.blkstat = w.blkstat;
         a.tag_slot = static_cast<int>((gl + t) & 1);
@@ -786,31 +837,33 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.first = (phase == 1 && t == 0) ? 1 : 0;
         return a;
     };
-    auto counts = [&](int64_t t) { return w.seg[t & 1].count; };
+    auto counts = [&](int64_t t) { return w.count_of(static_cast<int>(t % 3)); };
 
     int64_t n2 = 0;
     eik_status rc = run_loop(
         [&](int64_t t) {
             return timed(prof, EIK_KERNEL_UPDATE, [&] { return k.update(iter_args(t, 0), g, hT, eT, inner, s); });
         },
-        counts, GT, cap, async, s, &n2);
+        counts, kSub * kPad, cap, async, s, &n2);
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
-        // detection writes list 0 (consumed by remedy launch 0)
-        TileIter<T> d = iter_args(0, 1);
+        // detection fills list 0 of the remedy loop
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
+        TileIter<T> d = iter_args(0, 1);  // only `next` (list 0) and the tag are used
+        d.next = list_of(0);
         d.first = 0;
-        d.next = w.seg[0];
+        d.tag_slot = static_cast<int>(gl & 1);
         HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, g, hT, eT, s); }));
         gl += 1;
-        launched += 1;
+        launched += 2;
         int64_t n3 = 0;
         rc = run_loop(
             [&](int64_t t) {
                 return timed(prof, EIK_KERNEL_REMEDY,
                              [&] { return k.remedy(iter_args(t, 1), g, hT, eT, inner, s); });
             },
-            counts, GT, cap, async, s, &n3);
+            counts, kSub * kPad, cap, async, s, &n3);
         launched += n3;
     }
     if (async) return rc;
@@ -823,18 +876,18 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         *st = eik_stats{};
         st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
-        st->evals_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS2, GT));
+        st->evals_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS2, kMaxStatBlocks));
         st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : gd.n - static_cast<int64_t>(src.size());
-        st->evals_remedy = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS3, GT));
+        st->evals_remedy = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS3, kMaxStatBlocks));
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);
         st->launches = launched;
-        st->tile_visits_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS2, GT));
-        st->tile_visits_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS3, GT));
-        st->inner_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER2, GT));
-        st->inner_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER3, GT));
-        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, GT));
-        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, GT));
+        st->tile_visits_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS2, kMaxStatBlocks));
+        st->tile_visits_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS3, kMaxStatBlocks));
+        st->inner_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER2, kMaxStatBlocks));
+        st->inner_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER3, kMaxStatBlocks));
+        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, kMaxStatBlocks));
+        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, kMaxStatBlocks));
         HIP_TRY(prof.collect(st));
     }
     return rc;
