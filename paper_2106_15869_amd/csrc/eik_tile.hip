@@ -282,6 +282,66 @@ __device__ __forceinline__ void stat_add(unsigned long long* blkstat, int field,
 }
 
 // ---------------------------------------------------------------------------
+// In-tile work lists
+// ---------------------------------------------------------------------------
+// Nodes of a tile are numbered n = (z * TY + y) * TX + x.  The inner
+// iterations of a visit work on an LDS list of node ids instead of sweeping
+// all nodes: iteration it drains list it & 1 (length cnt[it % 3]) and appends
+// to list (it + 1) & 1; a per-list flag array keeps entries unique.  Only as
+// many waves as the list needs evaluate the local solver.
+template <int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void node_loc(int n, int& x, int& y, int& z, int& L) {
+    using S = Shape<ND, TX, TY, TZ>;
+    x = n % TX;
+    y = (n / TX) % TY;
+    z = ND == 3 ? n / (TX * TY) : 0;
+    L = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ int node_step(int d) {
+    switch (d) {
+        case 0: return -1;
+        case 1: return 1;
+        case 2: return -TX;
+        case 3: return TX;
+        case 4: return -TX * TY;
+        default: return TX * TY;
+    }
+}
+
+// bit d: the node lies on the tile face in direction d
+template <int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ int edge_bits(int x, int y, int z) {
+    int e = (x == 0 ? 1 : 0) | (x == TX - 1 ? 2 : 0) | (y == 0 ? 4 : 0) | (y == TY - 1 ? 8 : 0);
+    if (ND == 3) e |= (z == 0 ? 16 : 0) | (z == TZ - 1 ? 32 : 0);
+    return e;
+}
+
+// bit d: the grid continues past the tile face in direction d
+template <int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ int open_bits(const TileGeom& g, int x0, int y0, int z0) {
+    int f = (x0 > 0 ? 1 : 0) | (x0 + TX < g.nx ? 2 : 0) | (y0 > 0 ? 4 : 0) | (y0 + TY < g.ny ? 8 : 0);
+    if (ND == 3) f |= (z0 > 0 ? 16 : 0) | (z0 + TZ < g.nz ? 32 : 0);
+    return f;
+}
+
+template <int NT>
+struct TileLists {
+    uint32_t flag[2][NT];
+    uint16_t list[2][NT];
+    int cnt[3];
+};
+
+// Append node q to the next list once (returns whether it was added).
+template <int NT>
+__device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, int q) {
+    if (atomicExch(&tl.flag[nb][q], 1u) != 0u) return false;
+    tl.list[nb][atomicAdd(ncnt, 1)] = static_cast<uint16_t>(q);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // STEP 2 on tiles
 // ---------------------------------------------------------------------------
 template <typename T, int ND, int TX, int TY, int TZ>
@@ -290,6 +350,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
+    __shared__ T sH[S::NT];
+    __shared__ TileLists<S::NT> tl;
     __shared__ int s_len[kSub];
     __shared__ int s_slot;
     __shared__ int s_face;
@@ -309,92 +371,116 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         ++visits;
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
-        Owned<T, S::NPT> o;
-        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        bool ok[S::NPT];
+        int G[S::NPT], L[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            int x, y, z;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
+            ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+            G[r] = ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+            if (nn < S::NT) {
+                sH[nn] = ok[r] ? cell_H(h, a.F[G[r]]) : inf;
+                tl.flag[0][nn] = 0u;
+                tl.flag[1][nn] = 0u;
+            }
+        }
         if (threadIdx.x == 0) {
             s_face = 0;
             s_evals = 0;
             s_written = 0;
+            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
         }
         __syncthreads();
         uint8_t lab0[S::NPT];
         T phi0[S::NPT];
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            lab0[r] = o.ok[r] ? sl[o.L[r]] : uint8_t(0);
-            phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
-            if (o.ok[r] && o.H[r] < inf) sl[o.L[r]] = lab0[r] | kPass;
+            lab0[r] = ok[r] ? sl[L[r]] : uint8_t(0);
+            phi0[r] = ok[r] ? sphi[L[r]] : inf;
+            if (ok[r] && sH[threadIdx.x + r * kBlock] < inf) sl[L[r]] = lab0[r] | kPass;
         }
         __syncthreads();
-        // FAR nodes next to a converged / fixed node join the active set
+        // initial active list: active nodes, and FAR nodes next to a converged
+        // or fixed node (their activation was requested by a neighbour)
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            if (!o.ok[r]) continue;
-            const uint8_t me = sl[o.L[r]];
-            if ((me & 3u) != L_FAR || !(me & kPass)) continue;
-            bool act = false;
+            if (!ok[r]) continue;
+            const uint8_t me = sl[L[r]];
+            bool act = (me & 3u) == L_ACTIVE;
+            if ((me & 3u) == L_FAR && (me & kPass)) {
 #pragma unroll
-            for (int d = 0; d < 2 * ND; ++d) {
-                const uint8_t nb = sl[o.L[r] + lds_offset<ND, TX, TY, TZ>(d)];
-                const uint32_t st = nb & 3u;
-                act |= !(nb & kOut) && (st == L_CONV || st == L_FIXED);
+                for (int d = 0; d < 2 * ND; ++d) {
+                    const uint8_t nb = sl[L[r] + lds_offset<ND, TX, TY, TZ>(d)];
+                    const uint32_t st = nb & 3u;
+                    act |= !(nb & kOut) && (st == L_CONV || st == L_FIXED);
+                }
+                if (act) sl[L[r]] = (me & ~3u) | L_ACTIVE;
             }
-            if (act) sl[o.L[r]] = (me & ~3u) | L_ACTIVE;
+            if (act) tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(threadIdx.x + r * kBlock);
         }
         __syncthreads();
-        // Inner iterations, values updated in place in LDS: one barrier each.
-        // A node activated by a neighbour during an iteration is picked up in
-        // the same or the next one; reads racing with updates see either value,
-        // both upper bounds of the solution.
+        // Inner iterations on the LDS active list, values updated in place:
+        // one barrier each.  Reads racing with updates see either value, both
+        // upper bounds of the solution.
         bool any_active = false;
-        int my_evals = 0;
+        int my_evals = 0, fm = 0;
         int it = 0;
         for (;; ++it) {
-            bool has = false;
-            int fm = 0;
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                if (!o.ok[r]) continue;
-                const int L = o.L[r];
-                if ((sl[L] & 3u) != L_ACTIVE) continue;
-                has = true;
-                if (it == inner) continue;  // cap reached: leave it active
+            const int ncur = tl.cnt[it % 3];
+            if (ncur == 0) break;
+            if (it == inner) {
+                any_active = true;  // cap reached: the listed nodes stay active
+                break;
+            }
+            const int cb = it & 1, nb = cb ^ 1;
+            int* ncnt = &tl.cnt[(it + 1) % 3];
+            if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
                 ++my_evals;
-                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, L, o.H[r]);
-                const T cur = sphi[L];
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                const T cur = sphi[Lq];
                 if (pt < inf && cur - pt <= eps) {
-                    sl[L] = (sl[L] & ~3u) | L_CONV;
+                    // converged: joins Source; FAR neighbours become active
+                    sl[Lq] = (sl[Lq] & ~3u) | L_CONV;
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
                     for (int d = 0; d < 2 * ND; ++d) {
-                        const int q = L + lds_offset<ND, TX, TY, TZ>(d);
-                        const uint8_t nb = sl[q];
-                        if (o.face[r] & (1 << d)) {
-                            if ((nb & 3u) == L_FAR) fm |= 1 << d;  // neighbour tile must look
-                        } else if (!(nb & kOut) && (nb & 3u) == L_FAR && (nb & kPass)) {
-                            sl[q] = (nb & ~3u) | L_ACTIVE;
+                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                        const uint8_t lb = sl[Ln];
+                        if (edge & (1 << d)) {
+                            if ((open & (1 << d)) && (lb & 3u) == L_FAR) fm |= 1 << d;
+                        } else if (!(lb & kOut) && (lb & 3u) == L_FAR && (lb & kPass)) {
+                            if (list_add(tl, nb, ncnt, q + node_step<TX, TY>(d))) sl[Ln] = (lb & ~3u) | L_ACTIVE;
                         }
                     }
                 } else if (!(pt < inf)) {
-                    sl[L] = (sl[L] & ~3u) | L_FAR;
-                } else if (pt < cur) {
-                    sphi[L] = pt;
+                    sl[Lq] = (sl[Lq] & ~3u) | L_FAR;
+                } else {
+                    if (pt < cur) sphi[Lq] = pt;
+                    list_add(tl, nb, ncnt, q);
                 }
             }
-            if (fm) atomicOr(&s_face, fm);
-            any_active = __syncthreads_or(has);
-            if (!any_active || it == inner) break;
+            __syncthreads();
         }
+        if (fm) atomicOr(&s_face, fm);
         // write back what changed
         int my_written = 0;
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            if (!o.ok[r]) continue;
-            const uint8_t st = sl[o.L[r]] & 3u;
-            if (st != (lab0[r] & 3u)) a.lab[o.G[r]] = st;
-            const T v = sphi[o.L[r]];
+            if (!ok[r]) continue;
+            const uint8_t st = sl[L[r]] & 3u;
+            if (st != (lab0[r] & 3u)) a.lab[G[r]] = st;
+            const T v = sphi[L[r]];
             if (v != phi0[r]) {
-                a.phi[o.G[r]] = v;
+                a.phi[G[r]] = v;
                 ++my_written;
             }
         }
@@ -405,10 +491,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         // so the device atomics of one visit are in flight together
         if (threadIdx.x < 7) {
             const int d = threadIdx.x;
-            const int fm = s_face;
+            const int fmask = s_face;
             if (d == 6) {
                 if (any_active) push_tile(a.next, a.tstamp, t, ntag);
-            } else if (d < 2 * ND && (fm & (1 << d))) {
+            } else if (d < 2 * ND && (fmask & (1 << d))) {
                 push_tile(a.next, a.tstamp, neighbour_tile(g, t, d), ntag);
             }
         }
@@ -460,13 +546,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
 // ---------------------------------------------------------------------------
 // STEP 3: remedy loop on tiles
 // ---------------------------------------------------------------------------
+// The remedy rule restricted to the tile, on an LDS remedy list: a listed
+// node that drops takes the new value; its in-tile neighbours are listed for
+// the next iteration when the new value lies below theirs (otherwise their
+// update cannot change: the node is not upwind of them), and a face neighbour
+// below the halo value marks that face dirty in the tile across it.
 template <typename T, int ND, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom g, T h, T eps,
                                                         int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
-    __shared__ uint8_t snf[2][S::NL];  // flags for the next inner iteration (double buffered)
+    __shared__ T sH[S::NT];
+    __shared__ TileLists<S::NT> tl;
     __shared__ int s_len[kSub];
     __shared__ int s_slot;
     __shared__ int s_face;
@@ -486,75 +578,92 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         ++visits;
         const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         uint32_t mask_in = 0;
         if (threadIdx.x == 0) mask_in = atomicExch(a.tmask + t, 0u);  // in flight during staging
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
-        Owned<T, S::NPT> o;
-        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        bool ok[S::NPT];
+        int G[S::NPT], L[S::NPT], E[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            int x, y, z;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
+            E[r] = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
+            ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+            G[r] = ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+            if (nn < S::NT) {
+                sH[nn] = ok[r] ? cell_H(h, a.F[G[r]]) : inf;
+                tl.flag[0][nn] = 0u;
+                tl.flag[1][nn] = 0u;
+            }
+        }
         if (threadIdx.x == 0) {
             s_face = 0;
             s_evals = 0;
             s_written = 0;
             s_mask = mask_in;
+            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
         }
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r)
-            if (o.ok[r]) snf[0][o.L[r]] = snf[1][o.L[r]] = 0;
         __syncthreads();
+        // initial remedy list: every non-source node on a first visit, else the
+        // nodes on the faces whose neighbour tile changed
         const uint32_t m = s_mask;
-        bool live[S::NPT], fl[S::NPT];
         T phi0[S::NPT];
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            live[r] = o.ok[r] && (sl[o.L[r]] & 3u) != L_FIXED;
-            phi0[r] = o.ok[r] ? sphi[o.L[r]] : inf;
-            fl[r] = live[r] && ((m & kAllFaces) || (o.face[r] & static_cast<int>(m)));
+            phi0[r] = ok[r] ? sphi[L[r]] : inf;
+            const bool live = ok[r] && (sl[L[r]] & 3u) != L_FIXED;
+            if (live && ((m & kAllFaces) || (E[r] & static_cast<int>(m))))
+                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(threadIdx.x + r * kBlock);
         }
-        // Remedy iterations in place: a flagged node that drops takes the new
-        // value at once and flags itself and its in-tile neighbours in buffer
-        // it & 1, which every lane drains for its own nodes after the barrier.
+        __syncthreads();
         bool pending = false;
-        int my_evals = 0;
+        int my_evals = 0, fm = 0;
         int it = 0;
         for (;; ++it) {
-            bool has = false;
-            int fm = 0;
-            uint8_t* mark = snf[it & 1];
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                if (!fl[r]) continue;
+            const int ncur = tl.cnt[it % 3];
+            if (ncur == 0) break;
+            if (it == inner) {
+                pending = true;
+                break;
+            }
+            const int cb = it & 1, nb = cb ^ 1;
+            int* ncnt = &tl.cnt[(it + 1) % 3];
+            if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
                 ++my_evals;
-                const int L = o.L[r];
-                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, L, o.H[r]);
-                if (pt < sphi[L] - eps) {
-                    sphi[L] = pt;
-                    has = true;
-                    mark[L] = 1;
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                if (pt < sphi[Lq] - eps) {
+                    sphi[Lq] = pt;
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
-                    for (int d = 0; d < 2 * ND; ++d)
-                        if (!(o.edge[r] & (1 << d))) mark[L + lds_offset<ND, TX, TY, TZ>(d)] = 1;
-                    fm |= o.face[r];
+                    for (int d = 0; d < 2 * ND; ++d) {
+                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                        if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
+                        if (edge & (1 << d)) {
+                            if (open & (1 << d)) fm |= 1 << d;
+                        } else {
+                            const uint8_t lb = sl[Ln];
+                            if (!(lb & kOut) && (lb & 3u) != L_FIXED) list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
+                        }
+                    }
                 }
             }
-            if (fm) atomicOr(&s_face, fm);
-            pending = __syncthreads_or(has);
-            if (!pending || it == inner) break;
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                fl[r] = false;
-                if (o.ok[r]) {
-                    fl[r] = live[r] && mark[o.L[r]];
-                    mark[o.L[r]] = 0;
-                }
-            }
+            __syncthreads();
         }
+        if (fm) atomicOr(&s_face, fm);
         int my_written = 0;
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            if (!o.ok[r]) continue;
-            const T v = sphi[o.L[r]];
+            if (!ok[r]) continue;
+            const T v = sphi[L[r]];
             if (v != phi0[r]) {
-                a.phi[o.G[r]] = v;
+                a.phi[G[r]] = v;
                 ++my_written;
             }
         }
@@ -564,13 +673,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         // scheduling, one lane per target tile (see the update kernel)
         if (threadIdx.x < 7) {
             const int d = threadIdx.x;
-            const int fm = s_face;
+            const int fmask = s_face;
             if (d == 6) {
                 if (pending) {
                     atomicOr(a.tmask + t, kAllFaces);
                     push_tile(a.next, a.tstamp, t, ntag);
                 }
-            } else if (d < 2 * ND && (fm & (1 << d))) {
+            } else if (d < 2 * ND && (fmask & (1 << d))) {
                 const int tn = neighbour_tile(g, t, d);
                 atomicOr(a.tmask + tn, 1u << (d ^ 1));  // the face of tn shared with t
                 push_tile(a.next, a.tstamp, tn, ntag);
