@@ -333,21 +333,12 @@ struct TileLists {
     int cnt[3];
 };
 
-// Append the items selected by `mask` to list nb with one LDS atomic per
-// wave (lane prefix sum).  Every lane of the wave must call.
-template <int NT, int MAXC>
-__device__ __forceinline__ void list_append(TileLists<NT>& tl, int nb, int* ncnt, const int (&items)[MAXC],
-                                            uint32_t mask) {
-    const int c = __popc(mask);
-    const int incl = wave_incl_scan(c);
-    const int total = __shfl(incl, 63, 64);
-    if (total == 0) return;
-    int base = 0;
-    if (lane_id() == 63) base = atomicAdd(ncnt, total);
-    base = __shfl(base, 63, 64) + incl - c;
-#pragma unroll
-    for (int j = 0; j < MAXC; ++j)
-        if (mask & (1u << j)) tl.list[nb][base + __popc(mask & ((1u << j) - 1u))] = static_cast<uint16_t>(items[j]);
+// Append node q to the next list once (returns whether it was added).
+template <int NT>
+__device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, int q) {
+    if (atomicExch(&tl.flag[nb][q], 1u) != 0u) return false;
+    tl.list[nb][atomicAdd(ncnt, 1)] = static_cast<uint16_t>(q);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -448,51 +439,34 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             const int cb = it & 1, nb = cb ^ 1;
             int* ncnt = &tl.cnt[(it + 1) % 3];
             if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
-            for (int base = 0; base < ncur; base += kBlock) {
-                const int i = base + threadIdx.x;
-                int items[7];
-                uint32_t win = 0;
-                if (i < ncur) {
-                    const int q = tl.list[cb][i];
-                    tl.flag[cb][q] = 0u;
-                    int x, y, z, Lq;
-                    node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
-                    ++my_evals;
-                    const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
-                    const T cur = sphi[Lq];
-                    if (pt < inf && cur - pt <= eps) {
-                        // converged: joins Source; FAR neighbours become active
-                        sl[Lq] = (sl[Lq] & ~3u) | L_CONV;
-                        const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
-                        uint32_t cand = 0;
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+                ++my_evals;
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                const T cur = sphi[Lq];
+                if (pt < inf && cur - pt <= eps) {
+                    // converged: joins Source; FAR neighbours become active
+                    sl[Lq] = (sl[Lq] & ~3u) | L_CONV;
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
-                        for (int d = 0; d < 2 * ND; ++d) {
-                            const uint8_t lb = sl[Lq + lds_offset<ND, TX, TY, TZ>(d)];
-                            items[d] = q + node_step<TX, TY>(d);
-                            if (edge & (1 << d)) {
-                                if ((open & (1 << d)) && (lb & 3u) == L_FAR) fm |= 1 << d;
-                            } else if (!(lb & kOut) && (lb & 3u) == L_FAR && (lb & kPass)) {
-                                cand |= 1u << d;
-                            }
+                    for (int d = 0; d < 2 * ND; ++d) {
+                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                        const uint8_t lb = sl[Ln];
+                        if (edge & (1 << d)) {
+                            if ((open & (1 << d)) && (lb & 3u) == L_FAR) fm |= 1 << d;
+                        } else if (!(lb & kOut) && (lb & 3u) == L_FAR && (lb & kPass)) {
+                            if (list_add(tl, nb, ncnt, q + node_step<TX, TY>(d))) sl[Ln] = (lb & ~3u) | L_ACTIVE;
                         }
-#pragma unroll
-                        for (int d = 0; d < 2 * ND; ++d)
-                            if ((cand & (1u << d)) && atomicExch(&tl.flag[nb][items[d]], 1u) == 0u) win |= 1u << d;
-#pragma unroll
-                        for (int d = 0; d < 2 * ND; ++d) {
-                            if (!(win & (1u << d))) continue;
-                            const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                            sl[Ln] = (sl[Ln] & ~3u) | L_ACTIVE;
-                        }
-                    } else if (!(pt < inf)) {
-                        sl[Lq] = (sl[Lq] & ~3u) | L_FAR;
-                    } else {
-                        if (pt < cur) sphi[Lq] = pt;
-                        items[6] = q;
-                        if (atomicExch(&tl.flag[nb][q], 1u) == 0u) win = 1u << 6;
                     }
+                } else if (!(pt < inf)) {
+                    sl[Lq] = (sl[Lq] & ~3u) | L_FAR;
+                } else {
+                    if (pt < cur) sphi[Lq] = pt;
+                    list_add(tl, nb, ncnt, q);
                 }
-                list_append(tl, nb, ncnt, items, win);
             }
             __syncthreads();
         }
@@ -657,39 +631,28 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             const int cb = it & 1, nb = cb ^ 1;
             int* ncnt = &tl.cnt[(it + 1) % 3];
             if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
-            for (int base = 0; base < ncur; base += kBlock) {
-                const int i = base + threadIdx.x;
-                int items[6];
-                uint32_t win = 0;
-                if (i < ncur) {
-                    const int q = tl.list[cb][i];
-                    tl.flag[cb][q] = 0u;
-                    int x, y, z, Lq;
-                    node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
-                    ++my_evals;
-                    const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
-                    if (pt < sphi[Lq] - eps) {
-                        sphi[Lq] = pt;
-                        const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
-                        uint32_t cand = 0;
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+                ++my_evals;
+                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                if (pt < sphi[Lq] - eps) {
+                    sphi[Lq] = pt;
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
-                        for (int d = 0; d < 2 * ND; ++d) {
-                            const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                            items[d] = q + node_step<TX, TY>(d);
-                            if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
-                            if (edge & (1 << d)) {
-                                if (open & (1 << d)) fm |= 1 << d;
-                            } else {
-                                const uint8_t lb = sl[Ln];
-                                if (!(lb & kOut) && (lb & 3u) != L_FIXED) cand |= 1u << d;
-                            }
+                    for (int d = 0; d < 2 * ND; ++d) {
+                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                        if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
+                        if (edge & (1 << d)) {
+                            if (open & (1 << d)) fm |= 1 << d;
+                        } else {
+                            const uint8_t lb = sl[Ln];
+                            if (!(lb & kOut) && (lb & 3u) != L_FIXED) list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
                         }
-#pragma unroll
-                        for (int d = 0; d < 2 * ND; ++d)
-                            if ((cand & (1u << d)) && atomicExch(&tl.flag[nb][items[d]], 1u) == 0u) win |= 1u << d;
                     }
                 }
-                list_append(tl, nb, ncnt, items, win);
             }
             __syncthreads();
         }
