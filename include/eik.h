@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 1
+#define EIK_ABI_VERSION 2
 
 typedef enum {
     EIK_OK = 0,
@@ -61,14 +61,20 @@ typedef enum {
     EIK_VARIANT_NODE_LIST = 0,
     /* Same node rules scheduled tile by tile: each workgroup stages a tile and
        its one-cell halo in LDS and runs several inner iterations per launch. */
-    EIK_VARIANT_TILE = 1
+    EIK_VARIANT_TILE = 1,
+    /* The fast iterative method the paper improves on (Section 2.3), on the
+       same node lists: a node that converges has its non-active neighbours
+       evaluated at once, and any whose value drops (re)joins the active list;
+       there is no remedy step.  Same fixed point; a comparison baseline. */
+    EIK_VARIANT_FIM = 2
 } eik_variant;
 
 enum {
     /* Synchronous reads per iteration (every update of an iteration sees the
        previous iteration's values); bitwise reproducible.  Node-list only. */
     EIK_FLAG_DETERMINISTIC = 1u,
-    /* Diagnostic: return after the update step, skipping the remedy step. */
+    /* Diagnostic: return after the update step, skipping the remedy step
+       (not with EIK_VARIANT_FIM, which has none). */
     EIK_FLAG_SKIP_REMEDY = 2u,
     /* Enqueue only: no host synchronisation, no F check, no stats.  The caller
        must pass a workspace and synchronise the stream itself. */
@@ -104,6 +110,7 @@ typedef struct {
     int64_t inner_step3;
     int64_t written_step2;      /* node values written back to HBM in the update step */
     int64_t written_step3;      /* ... in the remedy loop */
+    int64_t evals_check;        /* FIM: evaluations of neighbours of converged nodes */
     int64_t kernel_launches[EIK_KERNEL_KINDS]; /* with EIK_FLAG_PROFILE */
     double kernel_ms[EIK_KERNEL_KINDS];        /* with EIK_FLAG_PROFILE: summed device time */
 } eik_stats;

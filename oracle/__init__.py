@@ -73,6 +73,8 @@ def _load():
         lib.eo_ifim.argtypes = [i, P, d, P, P, P, i64, d, i, i64, P, P]
         lib.eo_ifim_f.restype = i
         lib.eo_ifim_f.argtypes = [i, P, d, P, P, P, i64, d, i, i64, P, P]
+        lib.eo_fim.restype = i
+        lib.eo_fim.argtypes = [i, P, d, P, P, P, i64, d, i64, P, P]
         if hasattr(lib, "eo_adjoint"):
             lib.eo_adjoint.restype = i
             lib.eo_adjoint.argtypes = [i, P, d, P, P, i64, P, P, P, P]
@@ -179,6 +181,25 @@ def ifim(F, h: float, sources, values=None, eps: float = 0.0, skip_remedy: bool 
     if rc:
         raise ValueError("eo_ifim failed: %d" % rc)
     return phi, dict(zip(STAT_NAMES, (int(v) for v in stats)))
+
+
+FIM_STAT_NAMES = ("iters", "evals_update", "evals_check", "max_active")
+
+
+def fim(F, h: float, sources, values=None, eps: float = 0.0, max_iters: Optional[int] = None):
+    """The fast iterative method (Section 2.3), serial, synchronous reads per
+    iteration, float64; returns (phi, stats dict)."""
+    F64, dims, src, val = _prep(F, sources, values)
+    phi = np.empty(F64.shape, dtype=np.float64)
+    stats = np.zeros(len(FIM_STAT_NAMES), dtype=np.int64)
+    cap = int(max_iters) if max_iters is not None else 4 * F64.size + 16
+    rc = _load().eo_fim(F64.ndim, _ptr(dims), float(h), _ptr(F64), _ptr(src),
+                        None if val is None else _ptr(val), len(src), float(eps), cap, _ptr(phi), _ptr(stats))
+    if rc == EO_NOCONV:
+        raise RuntimeError("eo_fim: iteration cap reached")
+    if rc:
+        raise ValueError("eo_fim failed: %d" % rc)
+    return phi, dict(zip(FIM_STAT_NAMES, (int(v) for v in stats)))
 
 
 def adjoint(F, h: float, sources, phi, dL_dphi, values=None):

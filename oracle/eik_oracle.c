@@ -28,6 +28,13 @@
  *   eo_ifim  : the improved fast iterative method (Algorithm 2) emulated
  *       serially with synchronous (Jacobi) reads per iteration, in float64 or
  *       float32 arithmetic, with per-phase counters.
+ *   eo_fim   : the fast iterative method the paper improves on (Section
+ *       2.3), emulated serially: each iteration updates the active list with
+ *       synchronous reads; a node whose value no longer changes leaves the
+ *       list and each of its neighbours that is not active is evaluated at
+ *       once -- if its value drops it takes the new value and (re)joins the
+ *       active list.  Counters: iterations, active evaluations, neighbour-check
+ *       evaluations, peak list length.
  *   eo_adjoint : reverse sweep in fast-marching acceptance order giving
  *       dL/dF for a loss L(phi) (the linearised upwind system, transposed).
  *
@@ -523,6 +530,87 @@ int eo_ifim_f(int ndim, const int64_t* dims, double h, const double* F,
               const int64_t* src, const double* sval, int64_t nsrc, double eps,
               int skip_remedy, int64_t max_iters, float* phi, int64_t* stats) {
     IFIM_BODY(float, eo_godunov_f, axis_mins_f)
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fast iterative method (Section 2.3)                                        */
+/* ------------------------------------------------------------------------- */
+int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
+           const int64_t* src, const double* sval, int64_t nsrc, double eps,
+           int64_t max_iters, double* phi, int64_t* stats) {
+    grid_t g;
+    if (grid_init(&g, ndim, dims) || nsrc < 1 || !(h > 0.0)) return EO_BAD;
+    int64_t N = g.n;
+    unsigned char* lab = (unsigned char*)calloc((size_t)N, 1);
+    int64_t* A = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+    int64_t* B = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+    int64_t* C = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+    double* val = (double*)malloc((size_t)N * sizeof(double));
+    if (!lab || !A || !B || !C || !val) {
+        free(lab); free(A); free(B); free(C); free(val);
+        return EO_NOMEM;
+    }
+    for (int k = 0; k < 4; ++k) stats[k] = 0;
+    int rc = seed_sources(&g, src, sval, nsrc, phi, lab);
+    if (rc) goto done;
+    for (int64_t i = 0; i < N; ++i) lab[i] = lab[i] ? L_FIXED : L_FAR;
+    int64_t na = 0, nb = 0, nc = 0, nbr[6];
+    double a[3];
+    /* initialisation: the neighbours (F > 0) of the sources are active */
+    for (int64_t i = 0; i < N; ++i) {
+        if (lab[i] != L_FIXED) continue;
+        int c = neighbours(&g, i, nbr);
+        for (int t = 0; t < c; ++t) {
+            int64_t j = nbr[t];
+            if (lab[j] == L_FAR && F[j] > 0.0) { lab[j] = L_ACTIVE; A[na++] = j; }
+        }
+    }
+    while (na > 0) {
+        if (stats[0] >= max_iters) { rc = EO_NOCONV; goto done; }
+        stats[0] += 1;
+        stats[1] += na;
+        if (na > stats[3]) stats[3] = na;
+        /* update every active node from the values at the start of the iteration */
+        for (int64_t k = 0; k < na; ++k) {
+            int64_t i = A[k];
+            axis_mins(&g, phi, i, a);
+            val[k] = eo_godunov(g.nd, a, h / F[i]);
+        }
+        nb = nc = 0;
+        for (int64_t k = 0; k < na; ++k) {
+            int64_t i = A[k];
+            double pt = val[k];
+            if (pt < INFINITY && phi[i] - pt <= eps) {
+                lab[i] = L_CONV;          /* converged: leaves the active list */
+                C[nc++] = i;
+            } else if (!(pt < INFINITY)) {
+                lab[i] = L_FAR;
+            } else {
+                if (pt < phi[i]) phi[i] = pt;
+                B[nb++] = i;
+            }
+        }
+        /* neighbour check of the converged nodes, after the update */
+        for (int64_t k = 0; k < nc; ++k) {
+            int c = neighbours(&g, C[k], nbr);
+            for (int t = 0; t < c; ++t) {
+                int64_t j = nbr[t];
+                if (lab[j] == L_ACTIVE || lab[j] == L_FIXED || !(F[j] > 0.0)) continue;
+                stats[2] += 1;
+                axis_mins(&g, phi, j, a);
+                double q = eo_godunov(g.nd, a, h / F[j]);
+                if (q < phi[j] - eps) {
+                    phi[j] = q;
+                    lab[j] = L_ACTIVE;
+                    B[nb++] = j;
+                }
+            }
+        }
+        { int64_t* t_ = A; A = B; B = t_; na = nb; }
+    }
+done:
+    free(lab); free(A); free(B); free(C); free(val);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */

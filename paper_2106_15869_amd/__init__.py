@@ -38,13 +38,15 @@ EIK_FLOAT32 = 0
 EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
+EIK_VARIANT_FIM = 2
+EIK_ABI_VERSION = 2
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
 EIK_FLAG_PROFILE = 8
 
 VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
-            "tile": EIK_VARIANT_TILE}
+            "tile": EIK_VARIANT_TILE, "fim": EIK_VARIANT_FIM}
 
 # Entry points declared in include/eik.h
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
@@ -59,7 +61,7 @@ class EikStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
         "remedy_initial", "max_active", "launches", "tile_visits_step2", "tile_visits_step3",
-        "inner_step2", "inner_step3", "written_step2", "written_step3")] + [
+        "inner_step2", "inner_step3", "written_step2", "written_step3", "evals_check")] + [
         ("kernel_launches", ctypes.c_int64 * 5), ("kernel_ms", ctypes.c_double * 5)]
 
     def to_dict(self):
@@ -131,6 +133,9 @@ def _load():
     lib.eik_last_error.argtypes = []
     lib.eik_abi_version.restype = i32
     lib.eik_abi_version.argtypes = []
+    if lib.eik_abi_version() != EIK_ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.eik_abi_version()}, this binding expects "
+                          f"{EIK_ABI_VERSION}: rebuild it with `python -m paper_2106_15869_amd.build`")
     _lib = lib
     return lib
 

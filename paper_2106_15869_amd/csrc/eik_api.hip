@@ -64,8 +64,10 @@ static eik_options resolve(const eik_options* opt) {
 static eik_status check_options(const eik_options& o) {
     if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64)
         return fail(EIK_ERR_INVALID_ARGUMENT, "unknown dtype");
-    if (o.variant != EIK_VARIANT_NODE_LIST && o.variant != EIK_VARIANT_TILE)
+    if (o.variant != EIK_VARIANT_NODE_LIST && o.variant != EIK_VARIANT_TILE && o.variant != EIK_VARIANT_FIM)
         return fail(EIK_ERR_INVALID_ARGUMENT, "unknown variant");
+    if (o.variant == EIK_VARIANT_FIM && (o.flags & EIK_FLAG_SKIP_REMEDY))
+        return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_VARIANT_FIM has no remedy step to skip");
     if (o.max_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "max_iters must be >= 0");
     if (o.inner_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "inner_iters must be >= 0");
     if (o.flags & ~15u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
@@ -91,7 +93,7 @@ struct NodeWs {
     unsigned long long* blkstat;
     uint8_t* lab;
     uint32_t* stamp;
-    SegList seg[2];
+    SegList seg[3];  // two alternating lists; the third is FIM's converged list
     void* vals;
     size_t bytes;
 };
@@ -103,7 +105,7 @@ static int node_seg_cap(int64_t n) {
     return static_cast<int>(7 * ((n + kNodeSegs - 1) / kNodeSegs) + 512);
 }
 
-static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
+static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det, bool fim) {
     NodeWs w{};
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -116,7 +118,7 @@ static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det) {
     w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kNodeSegs));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.stamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(n)));
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < (fim ? 3 : 2); ++k) {
         w.seg[k].cap = cap;
         w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(kNodeSegs)));
         w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * kNodeSegs));
@@ -130,7 +132,8 @@ static size_t elem_size(eik_dtype d) { return d == EIK_FLOAT64 ? 8 : 4; }
 
 static size_t workspace_bytes(const Problem& P, const eik_options& o) {
     if (o.variant == EIK_VARIANT_TILE) return tile_workspace_bytes(P.g, o);
-    return node_layout(nullptr, P.n, elem_size(o.dtype), (o.flags & EIK_FLAG_DETERMINISTIC) != 0).bytes;
+    return node_layout(nullptr, P.n, elem_size(o.dtype), (o.flags & EIK_FLAG_DETERMINISTIC) != 0,
+                       o.variant == EIK_VARIANT_FIM).bytes;
 }
 
 // Scratch owned by the library when the caller passes no workspace.
@@ -172,7 +175,8 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
                                  const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
     const bool det = (o.flags & EIK_FLAG_DETERMINISTIC) != 0;
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
-    NodeWs w = node_layout(ws, P.n, sizeof(T), det);
+    const bool fim = o.variant == EIK_VARIANT_FIM;
+    NodeWs w = node_layout(ws, P.n, sizeof(T), det, fim);
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * P.n + 64;
     int64_t launched = 0;
 
@@ -213,6 +217,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         a.vals = static_cast<T*>(w.vals);
         a.cur = w.seg[t & 1];
         a.next = w.seg[(t + 1) & 1];
+        a.conv = w.seg[2];
         a.ctl = w.ctl;
         a.blkstat = w.blkstat;
         a.tag_slot = static_cast<int>(t & 1);
@@ -222,16 +227,18 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
     auto counts = [&](int64_t t) { return w.seg[t & 1].count; };
     const int per_iter = det ? 2 : 1;
 
-    // STEP 2
+    // STEP 2 (FIM: its update with the neighbour check, two launches per iteration)
     int64_t n2 = 0, n3 = 0;
     eik_status rc = run_loop(
         [&](int64_t t) {
-            return timed(prof, EIK_KERNEL_UPDATE,
-                         [&] { return launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); });
+            return timed(prof, EIK_KERNEL_UPDATE, [&] {
+                return fim ? launch_fim<T>(P.g, iter_args(t, t == 0), hT, eT, s)
+                           : launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s);
+            });
         },
         counts, kNodeSegs, cap, async, s, &n2);
-    launched += per_iter * n2;
-    if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
+    launched += (fim ? 2 : per_iter) * n2;
+    if (rc == EIK_OK && !fim && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // STEP 3a: whole-grid check into list 0
         HIP_TRY(timed(prof, EIK_KERNEL_DETECT,
                       [&] { return launch_detect<T>(P.g, F, phi, w.lab, hT, eT, w.seg[0], s); }));
@@ -256,7 +263,8 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
         st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
-        st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : P.n - static_cast<int64_t>(src.size());
+        st->evals_detect = (fim || (o.flags & EIK_FLAG_SKIP_REMEDY)) ? 0 : P.n - static_cast<int64_t>(src.size());
+        st->evals_check = static_cast<int64_t>(blk_sum(hs.blk, SF_CHECK, kNodeSegs));
         st->evals_remedy = static_cast<int64_t>(hs.ctl->evals_rem);
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);

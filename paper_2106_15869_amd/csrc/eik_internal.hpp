@@ -26,6 +26,7 @@ struct Ctl {
 // host sums the columns after the solve.
 enum StatField {
     SF_EVALS2 = 0, SF_EVALS3, SF_VISITS2, SF_VISITS3, SF_INNER2, SF_INNER3, SF_WRITTEN2, SF_WRITTEN3,
+    SF_CHECK,  // FIM: neighbour-check evaluations
     kStatFields
 };
 constexpr int kMaxStatBlocks = 2048;
@@ -60,6 +61,7 @@ struct NodeIter {
     T* vals;           // per-entry values (synchronous-read mode)
     SegList cur;
     SegList next;
+    SegList conv;      // FIM: nodes that converged in this iteration
     Ctl* ctl;
     unsigned long long* blkstat;  // [kStatFields][kNodeSegs]
     int tag_slot;      // parity of this iteration (remedy stamp tag slot)
@@ -93,6 +95,8 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
                               hipStream_t s);
+template <typename T>
+hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, T h, T eps, hipStream_t s);
 hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
 

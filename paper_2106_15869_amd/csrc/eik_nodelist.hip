@@ -417,6 +417,137 @@ __global__ __launch_bounds__(kBlock) void k_remedy_apply(NodeIter<T> a, GridDims
     app.publish(a.next);
 }
 
+// ---------------------------------------------------------------------------
+// FIM (Section 2.3), the method the improved variant is compared against.
+// One iteration is two launches:
+//   k_fim_update  every active node is updated; a node whose value no longer
+//                 changes (phi - phi~ <= eps) leaves the list and goes to the
+//                 converged list, the others keep the new value and stay;
+//   k_fim_check   every neighbour of a converged node that is not active is
+//                 evaluated; if its value drops it takes the new value and
+//                 (re)joins the active list.
+// Converged nodes can therefore be reactivated, and the loop ends with the
+// active list empty.  The check evaluations are the work the improved method
+// removes from the update step.
+// ---------------------------------------------------------------------------
+
+// phi[i] = min(phi[i], v) for any sign of the values.
+__device__ __forceinline__ void atomic_min_value(float* p, float v) {
+    unsigned int* w = reinterpret_cast<unsigned int*>(p);
+    unsigned int old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (v < __uint_as_float(old)) {
+        const unsigned int prev = atomicCAS(w, old, __float_as_uint(v));
+        if (prev == old) return;
+        old = prev;
+    }
+}
+__device__ __forceinline__ void atomic_min_value(double* p, double v) {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (v < __longlong_as_double(static_cast<long long>(old))) {
+        const unsigned long long prev =
+            atomicCAS(w, old, static_cast<unsigned long long>(__double_as_longlong(v)));
+        if (prev == old) return;
+        old = prev;
+    }
+}
+
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_fim_update(NodeIter<T> a, GridDims gd, T h, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt, s_cnt_conv;
+    __shared__ int s_w;
+    const Grid g = make_grid(gd);
+    SegAppender keep{&s_cnt}, conv{&s_cnt_conv};
+    keep.init();
+    conv.init();
+    if (threadIdx.x == 0) s_w = 0;
+    int written = 0;
+    int lo, hi;
+    list_prologue(a, s_pref, true, lo, hi);
+    const T inf = pos_inf<T>();
+    for (int base = lo; base < hi; base += kBlock) {
+        const int k = base + threadIdx.x;
+        int item[1] = {0};
+        uint32_t mkeep = 0, mconv = 0;
+        if (k < hi) {
+            const int i = seg_entry<G>(a.cur, s_pref, k);
+            item[0] = i;
+            int x, y, z;
+            decode<ND>(g, i, x, y, z);
+            const T pi = a.phi[i];
+            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+            if (pt < inf && pi - pt <= eps) {
+                label_add(a.lab, i, int(L_CONV) - int(L_ACTIVE));
+                mconv = 1u;
+            } else if (!(pt < inf)) {
+                label_add(a.lab, i, int(L_FAR) - int(L_ACTIVE));
+            } else {
+                if (pt < pi) {
+                    a.phi[i] = pt;
+                    ++written;
+                }
+                mkeep = 1u;
+            }
+        }
+        keep.push_mask<1>(a.next, item, mkeep);
+        conv.push_mask<1>(a.conv, item, mconv);
+    }
+    flush_written(a.blkstat, SF_WRITTEN2, &s_w, written);
+    keep.publish(a.next);
+    conv.publish(a.conv);
+}
+
+// Reads the converged list of this iteration and appends to the active list
+// after the entries k_fim_update published there.
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_fim_check(NodeIter<T> a, GridDims gd, T h, T eps) {
+    __shared__ int s_pref[G + 1];
+    __shared__ int s_cnt;
+    __shared__ int s_w, s_e;
+    const Grid g = make_grid(gd);
+    SegAppender app{&s_cnt};
+    app.resume(a.next);
+    if (threadIdx.x == 0) s_w = s_e = 0;
+    int written = 0, evals = 0;
+    const int n = seg_prefix<G>(a.conv.count, s_pref);
+    int lo, hi;
+    seg_slice(n, G, lo, hi);
+    for (int base = lo; base < hi; base += kBlock) {
+        const int k = base + threadIdx.x;
+        int items[6];
+        uint32_t mask = 0;
+        if (k < hi) {
+            const int i = seg_entry<G>(a.conv, s_pref, k);
+            int x, y, z;
+            decode<ND>(g, i, x, y, z);
+            uint32_t valid;
+            neighbour_slots<ND>(g, i, x, y, z, items, valid);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (!((valid >> j) & 1u)) continue;
+                const int q = items[j];
+                const uint32_t lb = label_get(a.lab, q);
+                if (lb == L_ACTIVE || lb == L_FIXED || !(a.F[q] > T(0))) continue;
+                int qx, qy, qz;
+                decode<ND>(g, q, qx, qy, qz);
+                ++evals;
+                const T pt = eval_node<T, ND>(a.phi, a.F, g, q, qx, qy, qz, h);
+                if (pt < a.phi[q] - eps) {
+                    atomic_min_value(a.phi + q, pt);
+                    ++written;
+                    if (label_cas(a.lab, q, lb, L_ACTIVE)) mask |= 1u << j;
+                }
+            }
+        }
+        app.push_mask<6>(a.next, items, mask);
+    }
+    if (evals) atomicAdd(&s_e, evals);
+    flush_written(a.blkstat, SF_WRITTEN2, &s_w, written);
+    if (threadIdx.x == 0) blk_add(a.blkstat, SF_CHECK, G, static_cast<unsigned long long>(s_e));
+    app.publish(a.next);
+}
+
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_apply_local(GridDims gd, const T* __restrict__ F,
                                                         const T* __restrict__ phi, T h,
@@ -554,6 +685,18 @@ hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, T h, T eps, hipStream_t s) {
+    if (g.nd == 2) {
+        hipLaunchKernelGGL((k_fim_update<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
+        hipLaunchKernelGGL((k_fim_check<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
+    } else {
+        hipLaunchKernelGGL((k_fim_update<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
+        hipLaunchKernelGGL((k_fim_check<T, 3>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, ctl);
     return hipGetLastError();
@@ -576,7 +719,8 @@ hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
     template hipError_t launch_remedy<T>(const GridDims&, const NodeIter<T>&, T, T, bool,          \
                                          hipStream_t);                                             \
     template hipError_t launch_apply_local<T>(const GridDims&, const T*, const T*, T, T*,          \
-                                              hipStream_t);
+                                              hipStream_t);                                        \
+    template hipError_t launch_fim<T>(const GridDims&, const NodeIter<T>&, T, T, hipStream_t);
 
 EIK_INST(float)
 EIK_INST(double)

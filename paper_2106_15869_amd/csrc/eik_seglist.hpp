@@ -70,6 +70,10 @@ struct SegAppender {
     __device__ __forceinline__ void init() {
         if (threadIdx.x == 0) *s_cnt = 0;
     }
+    // continue after what an earlier launch published into segment blockIdx.x
+    __device__ __forceinline__ void resume(const SegList& out) {
+        if (threadIdx.x == 0) *s_cnt = out.count[blockIdx.x];
+    }
     // every lane of the wave must call; `mask` selects items[j]
     template <int MAXC>
     __device__ __forceinline__ void push_mask(const SegList& out, const int (&items)[MAXC], uint32_t mask) {

@@ -70,7 +70,13 @@ struct TileIter {
     T* phi;
     uint8_t* lab;
     uint32_t* tstamp;
-    uint32_t* tmask;   // per tile: dirty faces (bit d) or kAllFaces
+    // Per tile dirty faces (bit d) or kAllFaces, double-buffered by launch
+    // parity: a launch reads and clears `mask_cur` of the tiles it visits and
+    // sets bits only in `mask_next`, which the next launch reads.  A bit set
+    // during a launch is therefore never consumed by a visit that may have
+    // staged the neighbour's values before the change that set it.
+    uint32_t* mask_cur;
+    uint32_t* mask_next;
     TList cur;
     TList next;
     int* zero_count;   // counters of the list two launches ahead: cleared by this launch
@@ -537,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
             flag |= pt < sphi[o.L[r]] - eps;
         }
         if (__syncthreads_or(flag) && threadIdx.x == 0) {
-            atomicOr(a.tmask + t, kAllFaces);
+            a.mask_next[t] = kAllFaces;  // one writer: the workgroup of tile t
             push_tile(a.next, a.tstamp, t, ntag);
         }
     }
@@ -580,7 +586,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         uint32_t mask_in = 0;
-        if (threadIdx.x == 0) mask_in = atomicExch(a.tmask + t, 0u);  // in flight during staging
+        if (threadIdx.x == 0) {
+            // written by the previous launch; no writer during this one
+            mask_in = a.mask_cur[t];
+            a.mask_cur[t] = 0u;
+        }
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         bool ok[S::NPT];
         int G[S::NPT], L[S::NPT], E[S::NPT];
@@ -676,12 +686,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             const int fmask = s_face;
             if (d == 6) {
                 if (pending) {
-                    atomicOr(a.tmask + t, kAllFaces);
+                    atomicOr(a.mask_next + t, kAllFaces);
                     push_tile(a.next, a.tstamp, t, ntag);
                 }
             } else if (d < 2 * ND && (fmask & (1 << d))) {
                 const int tn = neighbour_tile(g, t, d);
-                atomicOr(a.tmask + tn, 1u << (d ^ 1));  // the face of tn shared with t
+                atomicOr(a.mask_next + tn, 1u << (d ^ 1));  // the face of tn shared with t
                 push_tile(a.next, a.tstamp, tn, ntag);
             }
         }
@@ -767,7 +777,7 @@ struct TileWs {
     unsigned long long* blkstat;
     uint8_t* lab;
     uint32_t* tstamp;
-    uint32_t* tmask;
+    uint32_t* tmask;    // two arrays of ntiles dirty-face masks (by launch parity)
     int* data[2];       // two list buffers (alternating)
     int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}
     int cap;
@@ -792,7 +802,7 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
     w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
-    w.tmask = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
+    w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
     w.counters = reinterpret_cast<int*>(take(kCounterBytes));
     for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
     w.bytes = off;
@@ -885,7 +895,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s); }));
     // tile stamps and dirty-face masks are adjacent: clear both
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + g.ntiles), s);
+        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + 2 * static_cast<size_t>(g.ntiles)), s);
     }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
     launched += 5;
@@ -934,7 +944,8 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.phi = phi;
         a.lab = w.lab;
         a.tstamp = w.tstamp;
-        a.tmask = w.tmask;
+        a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * g.ntiles;
+        a.mask_next = w.tmask + static_cast<size_t>((t + 1) & 1) * g.ntiles;
         a.cur = list_of(t);
         a.next = list_of(t + 1);
         a.zero_count = w.count_of(static_cast<int>((t + 2) % 3));
@@ -959,8 +970,9 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // detection fills list 0 of the remedy loop
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
-        TileIter<T> d = iter_args(0, 1);  // only `next` (list 0) and the tag are used
+        TileIter<T> d = iter_args(0, 1);  // only `next` (list 0), its masks and the tag are used
         d.next = list_of(0);
+        d.mask_next = w.tmask;  // read by remedy launch 0
         d.first = 0;
         d.tag_slot = static_cast<int>(gl & 1);
         HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, g, hT, eT, s); }));

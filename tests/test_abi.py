@@ -36,7 +36,8 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert eik.eik_abi_version() == 1
+    header = int(re.search(r"#define EIK_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert eik.eik_abi_version() == header == eik.EIK_ABI_VERSION
     assert eik.eik_status_string(0) == "EIK_OK"
     assert eik.eik_status_string(2) == "EIK_ERR_NO_CONVERGENCE"
     assert eik.eik_status_string(99) == "EIK_UNKNOWN_STATUS"
@@ -54,7 +55,26 @@ def test_options_struct_layout():
     assert ctypes.sizeof(eik.EikOptions) == 80
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
-    assert ctypes.sizeof(eik.EikStats) == 112 + 80
+    assert ctypes.sizeof(eik.EikStats) == 120 + 80
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """Offsets and sizes of the ctypes mirrors equal what a C compiler makes
+    of include/eik.h."""
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "eik.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options), sizeof(eik_stats),'
+        ' offsetof(eik_options, max_iters), offsetof(eik_options, stats), offsetof(eik_stats, evals_check),'
+        ' offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms)); return 0; }\n')
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(eik.EikOptions), ctypes.sizeof(eik.EikStats), eik.EikOptions.max_iters.offset,
+            eik.EikOptions.stats.offset, eik.EikStats.evals_check.offset, eik.EikStats.kernel_launches.offset,
+            eik.EikStats.kernel_ms.offset]
+    assert got == want
 
 
 def test_workspace_size(lib):
@@ -65,6 +85,8 @@ def test_workspace_size(lib):
     od = eik.make_options(eik.EIK_FLOAT64, "node", deterministic=True)
     assert eik.eik_workspace_size((64, 64), od) >= ws + 8 * n
     assert eik.eik_workspace_size((7, 9, 5), eik.make_options(eik.EIK_FLOAT32, "tile")) > 0
+    # FIM keeps a third (converged) list
+    assert eik.eik_workspace_size((64, 64), eik.make_options(eik.EIK_FLOAT32, "fim")) >= ws + 4 * 7 * n
     # invalid shapes give 0
     assert eik.eik_workspace_size((0, 5), o) == 0
     assert eik.eik_workspace_size((5,), o) == 0
@@ -123,6 +145,14 @@ def test_invalid_options_rejected(lib):
     o.workspace_bytes = 1 << 30
     o.max_iters = 10
     assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT  # profile needs a sync
+    o = eik.make_options(eik.EIK_FLOAT32, "fim", skip_remedy=True)
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT  # FIM has no remedy
+    assert "remedy" in lib.eik_last_error().decode()
+    o = eik.make_options(eik.EIK_FLOAT32, "fim", deterministic=True)
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    o.variant = 3
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
 
 
 def test_bad_source_values_rejected(lib):

@@ -247,3 +247,58 @@ def test_ifim_iteration_cap_reported():
     P = W.lognormal_2d(32, dtype=np.float64)
     with pytest.raises(RuntimeError):
         oracle.ifim(P.F, P.h, P.sources, max_iters=3)
+
+
+# ---------------------------------------------------------------------------
+# FIM (Section 2.3), the method the improved variant is compared against
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("P", _workload_cases() + _random_cases(4, 4, base=950), ids=lambda P: P.name)
+def test_fim_reaches_the_fixed_point(P):
+    """FIM's neighbour check re-activates every node a converged neighbour
+    would lower, so it ends at the same fixed point as fast marching and as
+    the improved method (the paper compares their run times on identical
+    solutions)."""
+    ref = oracle.fmm(P.F, P.h, P.sources)
+    phi, st = oracle.fim(P.F, P.h, P.sources)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(phi))
+    if fin.any():
+        assert np.max(np.abs(phi[fin] - ref[fin])) <= 1e-14 * ref[fin].max() + 1e-300
+    phi_i, _ = oracle.ifim(P.F, P.h, P.sources)
+    assert np.array_equal(np.isfinite(phi_i), fin)
+    if fin.any():
+        assert np.max(np.abs(phi[fin] - phi_i[fin])) <= 1e-14 * ref[fin].max() + 1e-300
+
+
+def test_fim_checks_neighbours_during_the_update():
+    """Section 3.3: FIM evaluates the neighbours of every converged node inside
+    the update, work the improved method's update step leaves out.  At
+    constant speed from one source both are exact without any remedy, and
+    FIM's check evaluations exceed the improved method's whole detection
+    pass."""
+    P = W.tiny_constant()
+    ref = oracle.fmm(P.F, P.h, P.sources)
+    phi_f, sf = oracle.fim(P.F, P.h, P.sources, eps=P.eps)
+    phi_i, si = oracle.ifim(P.F, P.h, P.sources, eps=P.eps)
+    assert np.array_equal(phi_f, ref) and np.array_equal(phi_i, ref)
+    n = P.F.size
+    assert sf["evals_check"] > si["evals_detect"] == n - 1
+    assert sf["evals_update"] >= n - 1          # every reachable node is updated at least once
+    assert si["evals_remedy"] == 0
+
+
+def test_fim_barrier_and_unreachable():
+    """A node behind a wall of F = 0 is never activated (+inf); a source on a
+    barrier cell still spreads to its passable neighbours."""
+    F = np.ones((24, 24))
+    F[:, 12] = 0.0
+    F[5, 5] = 0.0
+    phi, _ = oracle.fim(F, 1.0, [5 * 24 + 5])
+    assert np.all(np.isinf(phi[:, 12:]))
+    assert np.array_equal(phi, oracle.fmm(F, 1.0, [5 * 24 + 5]))
+
+
+def test_fim_iteration_cap_reported():
+    P = W.lognormal_2d(32, dtype=np.float64)
+    with pytest.raises(RuntimeError):
+        oracle.fim(P.F, P.h, P.sources, max_iters=3)
