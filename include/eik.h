@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 2
+#define EIK_ABI_VERSION 3
 
 typedef enum {
     EIK_OK = 0,
@@ -186,6 +186,49 @@ eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64
 
 /* Device workspace (bytes) eik_adjoint needs; 0 on invalid arguments. */
 size_t eik_adjoint_workspace_size(int32_t ndim, const int64_t* dims, const eik_options* opt);
+
+/* One grid of a batch (eik_solve_batch / eik_adjoint_batch). */
+typedef struct {
+    int64_t dims[3];   /* extents in C order: (ny, nx, ignored) for ndim = 2,
+                          (nz, ny, nx) for ndim = 3 */
+    double h;          /* grid spacing of this grid (> 0, finite) */
+    int64_t n_sources; /* >= 1: this grid's sources are the next n_sources
+                          entries of the sources array */
+} eik_instance;
+
+/*
+ * eik_solve_batch -- eik_solve for n_inst independent grids in one call: the
+ * grids' tiles share the work lists of every launch, so small grids fill the
+ * GPU together and the loops run until the slowest grid is done.  Tile
+ * variant only (EIK_ERR_UNSUPPORTED otherwise).
+ *   F, phi_out  device, the grids back to back in the order of inst (grid k
+ *               starts after the nodes of grids 0..k-1), C order within a grid
+ *   ndim        2 or 3, shared by all grids
+ *   inst        host, n_inst >= 1 descriptions
+ *   sources     host, flat indices local to their grid, grouped by grid
+ *               (sum of inst[k].n_sources entries)
+ *   opt         as eik_solve; opt->source_values (if set) is parallel to
+ *               sources; stats are summed over the batch
+ * The total node count must be below 2^31.  Errors as eik_solve.
+ */
+eik_status eik_solve_batch(const void* F, int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                           const int64_t* sources, double eps, void* phi_out, const eik_options* opt);
+
+/* Device workspace (bytes) eik_solve_batch needs; 0 on invalid arguments. */
+size_t eik_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                                const eik_options* opt);
+
+/*
+ * eik_adjoint_batch -- eik_adjoint for the grids of a batch (same layout as
+ * eik_solve_batch): dL_dphi and dL_dF_out hold the grids back to back.
+ */
+eik_status eik_adjoint_batch(const void* F, const void* phi, int32_t ndim, const eik_instance* inst,
+                             int32_t n_inst, const int64_t* sources, const void* dL_dphi, void* dL_dF_out,
+                             const eik_options* opt);
+
+/* Device workspace (bytes) eik_adjoint_batch needs; 0 on invalid arguments. */
+size_t eik_adjoint_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                                        const eik_options* opt);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_status_string(eik_status s);

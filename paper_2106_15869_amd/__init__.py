@@ -10,10 +10,12 @@ Functions mirror the C entry points:
 * ``eik_solve``        Algorithm 2 (initialisation, update, remedy).
 * ``eik_apply_local``  one dense pass of the exact Godunov local solve.
 * ``eik_adjoint``      dL/dF at a converged solution.
+* ``eik_solve_batch`` / ``eik_adjoint_batch``  the same for many grids at once.
 * ``eik_workspace_size``, ``eik_status_string``, ``eik_abi_version``.
 
-``solve`` / ``apply_local`` / ``adjoint`` are the tensor-level wrappers and
-``EikonalFn`` the autograd function built on ``eik_solve`` + ``eik_adjoint``.
+``solve`` / ``apply_local`` / ``adjoint`` / ``solve_batch`` / ``adjoint_batch``
+are the tensor-level wrappers and ``EikonalFn`` the autograd function built on
+``eik_solve`` + ``eik_adjoint``.
 """
 
 from __future__ import annotations
@@ -39,7 +41,7 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 2
+EIK_ABI_VERSION = 3
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
@@ -51,10 +53,16 @@ VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
 # Entry points declared in include/eik.h
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
            "eik_adjoint", "eik_adjoint_workspace_size", "eik_status_string", "eik_last_error",
-           "eik_abi_version")
+           "eik_abi_version", "eik_solve_batch", "eik_batch_workspace_size", "eik_adjoint_batch",
+           "eik_adjoint_batch_workspace_size")
 
 
 KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
+
+
+class EikInstance(ctypes.Structure):
+    """eik_instance: one grid of a batch."""
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("h", ctypes.c_double), ("n_sources", ctypes.c_int64)]
 
 
 class EikStats(ctypes.Structure):
@@ -133,6 +141,15 @@ def _load():
     lib.eik_last_error.argtypes = []
     lib.eik_abi_version.restype = i32
     lib.eik_abi_version.argtypes = []
+    IP = ctypes.POINTER(EikInstance)
+    lib.eik_solve_batch.restype = ctypes.c_int
+    lib.eik_solve_batch.argtypes = [P, i32, IP, i32, P, d, P, OP]
+    lib.eik_batch_workspace_size.restype = ctypes.c_size_t
+    lib.eik_batch_workspace_size.argtypes = [i32, IP, i32, OP]
+    lib.eik_adjoint_batch.restype = ctypes.c_int
+    lib.eik_adjoint_batch.argtypes = [P, P, i32, IP, i32, P, P, P, OP]
+    lib.eik_adjoint_batch_workspace_size.restype = ctypes.c_size_t
+    lib.eik_adjoint_batch_workspace_size.argtypes = [i32, IP, i32, OP]
     if lib.eik_abi_version() != EIK_ABI_VERSION:
         raise ImportError(f"{LIB_PATH} has ABI version {lib.eik_abi_version()}, this binding expects "
                           f"{EIK_ABI_VERSION}: rebuild it with `python -m paper_2106_15869_amd.build`")
@@ -229,17 +246,22 @@ def _sources_array(sources, shape) -> np.ndarray:
 def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = "tile",
           source_values=None, deterministic: bool = False, skip_remedy: bool = False,
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
-          out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False):
+          out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False,
+          async_: bool = False):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
-    (and a stats dict when stats=True)."""
+    (and a stats dict when stats=True).  async_=True only enqueues (no host
+    synchronisation, capturable in a graph): it needs `workspace`, `out` and
+    an explicit `max_iters`, and runs exactly max_iters launches per loop."""
     torch = _torch()
     _check_device_tensor(F, "F")
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, profile=profile)
+                       skip_remedy, async_=async_, profile=profile)
+    if async_ and (workspace is None or out is None):
+        raise ValueError("async_ needs a preallocated workspace and out")
     dims = _dims(F.shape)
     src = _sources_array(sources, F.shape)
     vals = None
@@ -293,14 +315,17 @@ def eik_adjoint_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] =
 
 
 def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats: bool = False,
-            stream=None, profile: bool = False):
-    """dL/dF at the converged solution phi (same F, h, sources)."""
+            stream=None, profile: bool = False, async_: bool = False, max_iters: int = 0):
+    """dL/dF at the converged solution phi (same F, h, sources).  async_ as in
+    solve()."""
     torch = _torch()
     for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
         _check_device_tensor(t, n)
         if t.shape != F.shape or t.dtype != F.dtype:
             raise ValueError(f"{n} must match F in shape and dtype")
-    opt = make_options(_dtype_code(F), profile=profile)
+    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile)
+    if async_ and (workspace is None or out is None):
+        raise ValueError("async_ needs a preallocated workspace and out")
     s = stream if stream is not None else torch.cuda.current_stream(F.device)
     opt.stream = s.cuda_stream
     need = eik_adjoint_workspace_size(F.shape, opt)
@@ -319,6 +344,141 @@ def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats:
         rc = _load().eik_adjoint(F.data_ptr(), phi.data_ptr(), F.dim(), _np_ptr(dims), float(h),
                                  _np_ptr(src), len(src), dL_dphi.data_ptr(), res.data_ptr(),
                                  ctypes.byref(opt))
+    _check(rc)
+    return (res, st.to_dict()) if stats else res
+
+
+# ---------------------------------------------------------------------------
+# batches: several independent grids solved together
+# ---------------------------------------------------------------------------
+
+def _instances(shapes, h, sources):
+    shapes = [tuple(int(v) for v in sh) for sh in shapes]
+    if not shapes:
+        raise ValueError("need at least one grid")
+    nd = len(shapes[0])
+    if nd not in (2, 3) or any(len(sh) != nd for sh in shapes):
+        raise ValueError("all grids must be 2D, or all 3D")
+    hs = [float(h)] * len(shapes) if np.isscalar(h) else [float(v) for v in h]
+    if len(hs) != len(shapes) or len(sources) != len(shapes):
+        raise ValueError("h (if a list) and sources need one entry per grid")
+    arr = (EikInstance * len(shapes))()
+    src = []
+    for k, sh in enumerate(shapes):
+        sk = _sources_array(sources[k], sh)
+        for j in range(nd):
+            arr[k].dims[j] = sh[j]
+        arr[k].h = hs[k]
+        arr[k].n_sources = len(sk)
+        src.append(sk)
+    return nd, arr, np.ascontiguousarray(np.concatenate(src).astype(np.int64)), shapes
+
+
+def batch_sizes(shapes) -> list:
+    """Node count of every grid (offsets of the packed layout are their prefix sums)."""
+    return [int(np.prod(sh)) for sh in shapes]
+
+
+def pack(tensors):
+    """Grids back to back in one flat device tensor (the batch layout)."""
+    torch = _torch()
+    return torch.cat([t.reshape(-1) for t in tensors])
+
+
+def unpack(flat, shapes):
+    """Views of the grids of a packed batch tensor."""
+    out, o = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(flat[o:o + n].view(*sh))
+        o += n
+    return out
+
+
+def eik_batch_workspace_size(shapes, h, sources, opt: Optional[EikOptions] = None) -> int:
+    nd, arr, _, _ = _instances(shapes, h, sources)
+    return int(_load().eik_batch_workspace_size(nd, arr, len(arr), ctypes.byref(opt) if opt is not None else None))
+
+
+def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
+                tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0, out=None,
+                workspace=None, stats: bool = False, stream=None, profile: bool = False, async_: bool = False):
+    """Solve several independent grids in one call (tile schedule).
+
+    F: flat device tensor with the grids back to back (see pack()); shapes:
+    one shape per grid; h: a spacing or one per grid; sources: per grid, flat
+    indices local to that grid (or coordinate arrays).  Returns the packed phi
+    (and summed stats)."""
+    torch = _torch()
+    _check_device_tensor(F, "F")
+    nd, arr, src, shapes = _instances(shapes, h, sources)
+    if F.numel() != sum(batch_sizes(shapes)):
+        raise ValueError("F must hold exactly the grids of the batch")
+    opt = make_options(_dtype_code(F), "tile", tile, inner_iters, max_iters, async_=async_, profile=profile)
+    if async_ and (workspace is None or out is None):
+        raise ValueError("async_ needs a preallocated workspace and out")
+    vals = None
+    if source_values is not None:
+        vals = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.float64).ravel()
+                                                    for v in source_values]))
+        if vals.shape != src.shape:
+            raise ValueError("source_values must match sources")
+        opt.source_values = vals.ctypes.data
+    phi = out if out is not None else torch.empty_like(F)
+    _check_device_tensor(phi, "out")
+    need = int(_load().eik_batch_workspace_size(nd, arr, len(arr), ctypes.byref(opt)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    elif workspace.numel() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    st = EikStats()
+    opt.stats = ctypes.pointer(st)
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    with torch.cuda.device(F.device):
+        rc = _load().eik_solve_batch(F.data_ptr(), nd, arr, len(arr), _np_ptr(src), float(eps), phi.data_ptr(),
+                                     ctypes.byref(opt))
+    _check(rc)
+    return (phi, st.to_dict()) if stats else phi
+
+
+def eik_adjoint_batch_workspace_size(shapes, h, sources, opt: Optional[EikOptions] = None) -> int:
+    nd, arr, _, _ = _instances(shapes, h, sources)
+    return int(_load().eik_adjoint_batch_workspace_size(nd, arr, len(arr),
+                                                        ctypes.byref(opt) if opt is not None else None))
+
+
+def adjoint_batch(F, phi, shapes, h, sources, dL_dphi, *, out=None, workspace=None, stats: bool = False,
+                  stream=None, profile: bool = False, async_: bool = False, max_iters: int = 0):
+    """dL/dF for every grid of a batch (packed layout as solve_batch)."""
+    torch = _torch()
+    for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
+        _check_device_tensor(t, n)
+        if t.shape != F.shape or t.dtype != F.dtype:
+            raise ValueError(f"{n} must match F in shape and dtype")
+    nd, arr, src, shapes = _instances(shapes, h, sources)
+    if F.numel() != sum(batch_sizes(shapes)):
+        raise ValueError("F must hold exactly the grids of the batch")
+    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile)
+    if async_ and (workspace is None or out is None):
+        raise ValueError("async_ needs a preallocated workspace and out")
+    need = int(_load().eik_adjoint_batch_workspace_size(nd, arr, len(arr), ctypes.byref(opt)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    elif workspace.numel() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    st = EikStats()
+    opt.stats = ctypes.pointer(st)
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    res = out if out is not None else torch.empty_like(F)
+    with torch.cuda.device(F.device):
+        rc = _load().eik_adjoint_batch(F.data_ptr(), phi.data_ptr(), nd, arr, len(arr), _np_ptr(src),
+                                       dL_dphi.data_ptr(), res.data_ptr(), ctypes.byref(opt))
     _check(rc)
     return (res, st.to_dict()) if stats else res
 

@@ -8,8 +8,10 @@
 //     lambda = dL/dphi + M^T lambda,
 // a triangular system in causal order.
 //
-//   k_adj_prep   dense: per node the upwind neighbour on each axis (lower
-//                index on a tie), the weights c_ik = w_ik / W_i and D_i.
+//   k_adj_prep   per node, tile by tile: the upwind neighbour on each axis
+//                (lower index on a tie), the weights c_ik = w_ik / W_i, D_i.
+//   Grids of a batch are tiled back to back (see eik_tile.hpp); every kernel
+//   looks up the instance of the tile it works on.
 //   k_adj_tile   tile worklist: each workgroup stages lambda and the stencil
 //                data of a tile plus halo in LDS and iterates
 //                lambda_j = g_j + sum_{i : j upwind of i} c_{i,axis} lambda_i
@@ -23,6 +25,8 @@
 #include "eik_device.hpp"
 #include "eik_host.hpp"
 #include "eik_seglist.hpp"
+#include "eik_batch.hpp"
+#include "eik_tile.hpp"
 
 namespace eik {
 
@@ -32,12 +36,6 @@ constexpr int GA = 1024;          // workgroups (list segments) per tile launch
 constexpr uint8_t kSrc = 0x80u;   // stencil byte: node is a source
 // stencil byte bits: axis k present -> bit 2k; upwind on the + side -> bit 2k+1
 // (axis 0 = x, 1 = y, 2 = z)
-
-struct AdjGeom {
-    int nx, ny, nz;
-    int ntx, nty, ntz;
-    int ntiles;
-};
 
 template <typename T>
 struct AdjArgs {
@@ -55,59 +53,67 @@ struct AdjArgs {
 };
 
 // ---------------------------------------------------------------------------
-template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_adj_prep(GridDims gd, const T* __restrict__ F,
-                                                     const T* __restrict__ phi, T h, uint8_t* up,
-                                                     T* coef, T* D, T* lam, const T* __restrict__ g) {
-    const Grid G = {gd.nx, gd.ny, gd.nz, gd.n, gd.nx * gd.ny};
+template <typename T, int ND, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_adj_prep(BatchGeom<T> bg, const T* __restrict__ F,
+                                                     const T* __restrict__ phi, uint8_t* up, T* coef, T* D,
+                                                     T* lam, const T* __restrict__ g) {
+    constexpr int NT = TX * TY * (ND == 3 ? TZ : 1);
     const T inf = pos_inf<T>();
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < G.n; i += gridDim.x * kBlock) {
-        int x, y, z;
-        decode<ND>(G, i, x, y, z);
-        const T p = phi[i];
-        const T f = F[i];
-        uint8_t u = 0;
-        T w[3] = {T(0), T(0), T(0)};
-        T W = T(0);
-        if (p < inf && f > T(0)) {
-            const int st[3] = {1, G.nx, G.sxy};
-            const int cc[3] = {x, y, z};
-            const int dd[3] = {G.nx, G.ny, G.nz};
+    for (int t = blockIdx.x; t < bg.ntiles; t += gridDim.x) {
+        const Inst<T> I = inst_of(bg, t);
+        const int lt = t - I.tile_base;
+        const int x0 = (lt % I.ntx) * TX, y0 = ((lt / I.ntx) % I.nty) * TY;
+        const int z0 = ND == 3 ? (lt / (I.ntx * I.nty)) * TZ : 0;
+        for (int q = threadIdx.x; q < NT; q += kBlock) {
+            const int x = x0 + q % TX, y = y0 + (q / TX) % TY, z = ND == 3 ? z0 + q / (TX * TY) : 0;
+            if (x >= I.nx || y >= I.ny || z >= I.nz) continue;
+            const int sy = I.nx, sz = I.nx * I.ny;
+            const int i = I.node_base + (z * I.ny + y) * I.nx + x;
+            const T p = phi[i];
+            const T f = F[i];
+            uint8_t u = 0;
+            T w[3] = {T(0), T(0), T(0)};
+            T W = T(0);
+            if (p < inf && f > T(0)) {
+                const int st[3] = {1, sy, sz};
+                const int cc[3] = {x, y, z};
+                const int dd[3] = {I.nx, I.ny, I.nz};
 #pragma unroll
-            for (int k = 0; k < ND; ++k) {
-                T v = inf;
-                int side = -1;
-                if (cc[k] > 0 && phi[i - st[k]] < v) {
-                    v = phi[i - st[k]];
-                    side = 0;
-                }
-                if (cc[k] + 1 < dd[k] && phi[i + st[k]] < v) {
-                    v = phi[i + st[k]];
-                    side = 1;
-                }
-                if (side >= 0 && v < p) {
-                    u |= static_cast<uint8_t>((1u << (2 * k)) | (static_cast<uint32_t>(side) << (2 * k + 1)));
-                    w[k] = p - v;
-                    W = W + w[k];
+                for (int k = 0; k < ND; ++k) {
+                    T v = inf;
+                    int side = -1;
+                    if (cc[k] > 0 && phi[i - st[k]] < v) {
+                        v = phi[i - st[k]];
+                        side = 0;
+                    }
+                    if (cc[k] + 1 < dd[k] && phi[i + st[k]] < v) {
+                        v = phi[i + st[k]];
+                        side = 1;
+                    }
+                    if (side >= 0 && v < p) {
+                        u |= static_cast<uint8_t>((1u << (2 * k)) | (static_cast<uint32_t>(side) << (2 * k + 1)));
+                        w[k] = p - v;
+                        W = W + w[k];
+                    }
                 }
             }
-        }
-        T d = T(0);
-        if (u && W > T(0)) {
-            const T Hh = h / f;
-            d = -(Hh * Hh) / (f * W);
+            T d = T(0);
+            if (u && W > T(0)) {
+                const T Hh = I.h / f;
+                d = -(Hh * Hh) / (f * W);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) w[k] = w[k] / W;
-        } else {
-            u = 0;
-            w[0] = w[1] = w[2] = T(0);
+                for (int k = 0; k < 3; ++k) w[k] = w[k] / W;
+            } else {
+                u = 0;
+                w[0] = w[1] = w[2] = T(0);
+            }
+            up[i] = u;
+            coef[3 * static_cast<size_t>(i) + 0] = w[0];
+            coef[3 * static_cast<size_t>(i) + 1] = w[1];
+            coef[3 * static_cast<size_t>(i) + 2] = w[2];
+            D[i] = d;
+            lam[i] = g[i];
         }
-        up[i] = u;
-        coef[3 * static_cast<size_t>(i) + 0] = w[0];
-        coef[3 * static_cast<size_t>(i) + 1] = w[1];
-        coef[3 * static_cast<size_t>(i) + 2] = w[2];
-        D[i] = d;
-        lam[i] = g[i];
     }
 }
 
@@ -145,21 +151,23 @@ __device__ __forceinline__ bool claim_t(uint32_t* ts, int t, uint32_t tag) {
 
 // Initial list: tiles holding a nonzero dL/dphi.
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_seed(AdjArgs<T> a, AdjGeom g) {
+__global__ __launch_bounds__(kBlock) void k_adj_seed(AdjArgs<T> a, BatchGeom<T> bg) {
     using S = AShape<ND, TX, TY, TZ>;
     __shared__ int s_cnt;
     SegAppender app{&s_cnt};
     app.init();
     __syncthreads();
     int lo, hi;
-    seg_slice(g.ntiles, GA, lo, hi);
+    seg_slice(bg.ntiles, GA, lo, hi);
     for (int t = lo; t < hi; ++t) {
-        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         bool nz = false;
         for (int q = threadIdx.x; q < S::NT; q += kBlock) {
             const int x = tx * TX + q % TX, y = ty * TY + (q / TX) % TY;
             const int z = ND == 3 ? tz * TZ + q / (TX * TY) : 0;
-            if (x < g.nx && y < g.ny && z < g.nz) nz |= a.g[(z * g.ny + y) * g.nx + x] != T(0);
+            if (x < g.nx && y < g.ny && z < g.nz) nz |= a.g[g.node_base + (z * g.ny + y) * g.nx + x] != T(0);
         }
         if (__syncthreads_or(nz) && threadIdx.x == 0 && claim_t(a.tstamp, t, 1u)) app.push_one(a.next, t);
     }
@@ -168,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(AdjArgs<T> a, AdjGeom g) {
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, AdjGeom g, int inner) {
+__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, BatchGeom<T> bg, int inner) {
     using S = AShape<ND, TX, TY, TZ>;
     __shared__ T slam[S::NL];
     __shared__ T scoef[3 * S::NL];
@@ -191,14 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, AdjGeom g, in
     const int sty = S::LX, stz = S::LX * S::LY;
     for (int e = lo; e < hi; ++e) {
         const int t = seg_entry<GA>(a.cur, s_pref, e);
-        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         for (int q = threadIdx.x; q < S::NL; q += kBlock) {
             const int lx = q % S::LX, ly = (q / S::LX) % S::LY, lz = q / (S::LX * S::LY);
             const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
             const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
             if (in) {
-                const int G = (gz * g.ny + gy) * g.nx + gx;
+                const int G = g.node_base + (gz * g.ny + gy) * g.nx + gx;
                 slam[q] = a.lam[G];
                 sup[q] = a.up[G];
                 scoef[3 * q + 0] = a.coef[3 * static_cast<size_t>(G) + 0];
@@ -220,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, AdjGeom g, in
             const int x = nn % TX, y = (nn / TX) % TY, z = ND == 3 ? nn / (TX * TY) : 0;
             const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
             ok[r] = nn < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
-            Gr[r] = (gz * g.ny + gy) * g.nx + gx;
+            Gr[r] = g.node_base + (gz * g.ny + gy) * g.nx + gx;
             Lr[r] = ((ND == 3 ? z + 1 : 0) * S::LY + (y + 1)) * S::LX + (x + 1);
             int f = 0;
             if (x == 0 && gx > 0) f |= 1;
@@ -321,92 +331,76 @@ struct AdjWs {
     void* lam;
     uint32_t* tstamp;
     SegList seg[2];
+    void* table;
+    int* tile_inst;
     size_t bytes;
 };
 
-void adj_tile(int nd, int& tx, int& ty, int& tz) {
-    if (nd == 2) {
-        tx = 32;
-        ty = 32;
-        tz = 1;
-    } else {
-        tx = ty = tz = 8;
-    }
-}
+TileCfg adj_tile(int nd) { return nd == 2 ? TileCfg{32, 32, 1} : TileCfg{8, 8, 8}; }
 
-AdjGeom adj_geom(const GridDims& gd) {
-    int tx, ty, tz;
-    adj_tile(gd.nd, tx, ty, tz);
-    AdjGeom g;
-    g.nx = gd.nx;
-    g.ny = gd.ny;
-    g.nz = gd.nz;
-    g.ntx = (gd.nx + tx - 1) / tx;
-    g.nty = (gd.ny + ty - 1) / ty;
-    g.ntz = (gd.nz + tz - 1) / tz;
-    g.ntiles = g.ntx * g.nty * g.ntz;
-    return g;
-}
-
-AdjWs adj_layout(char* base, const GridDims& gd, size_t esz) {
-    AdjGeom g = adj_geom(gd);
+AdjWs adj_layout(char* base, const Batch& b, size_t esz) {
     AdjWs w{};
     size_t off = 0;
-    auto take = [&](size_t b) {
+    auto take = [&](size_t n) {
         char* p = base ? base + off : nullptr;
-        off = align_up(off + b, 256);
+        off = align_up(off + n, 256);
         return p;
     };
-    const size_t n = static_cast<size_t>(gd.n);
-    const int cap = 7 * ((g.ntiles + GA - 1) / GA) + 512;
+    const size_t n = static_cast<size_t>(b.n);
+    const int cap = static_cast<int>(7 * ((b.ntiles + GA - 1) / GA) + 512);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.up = reinterpret_cast<uint8_t*>(take(n));
     w.coef = take(3 * esz * n);
     w.D = take(esz * n);
     w.lam = take(esz * n);
-    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(g.ntiles)));
+    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(b.ntiles)));
     for (int k = 0; k < 2; ++k) {
         w.seg[k].cap = cap;
         w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(GA)));
         w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * GA));
+    }
+    if (b.inst.size() > 1) {
+        w.table = take((esz == 8 ? sizeof(Inst<double>) : sizeof(Inst<float>)) * b.inst.size());
+        w.tile_inst = reinterpret_cast<int*>(take(4 * static_cast<size_t>(b.ntiles)));
     }
     w.bytes = off;
     return w;
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
-eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
-                   const std::vector<std::pair<int, double>>& src, const T* g, T* out,
-                   const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
+eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out, const eik_options& o, char* ws,
+                   hipStream_t s, eik_stats* st) {
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
-    AdjGeom G = adj_geom(gd);
-    AdjWs w = adj_layout(ws, gd, sizeof(T));
-    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * static_cast<int64_t>(gd.n) + 64;
+    AdjWs w = adj_layout(ws, b, sizeof(T));
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * b.n + 64;
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (TX + TY + TZ);
-    const int dense = static_cast<int>(std::min<int64_t>((gd.n + kBlock - 1) / kBlock, 1 << 20));
+    const int dense = static_cast<int>(std::min<int64_t>((b.n + kBlock - 1) / kBlock, 1 << 20));
+    const int tiles = static_cast<int>(std::min<int64_t>(b.ntiles, 1 << 16));
     int64_t launched = 0;
     Profiler prof;
     prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
 
+    BatchGeom<T> G;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return upload_batch_geom<T>(b, w.table, w.tile_inst, s, G, launched); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        hipLaunchKernelGGL((k_adj_prep<T, ND>), dim3(dense), dim3(kBlock), 0, s, gd, F, phi, static_cast<T>(h),
-                           w.up, static_cast<T*>(w.coef), static_cast<T*>(w.D), static_cast<T*>(w.lam), g);
+        hipLaunchKernelGGL((k_adj_prep<T, ND, TX, TY, TZ>), dim3(tiles), dim3(kBlock), 0, s, G, F, phi, w.up,
+                           static_cast<T*>(w.coef), static_cast<T*>(w.D), static_cast<T*>(w.lam), g);
         return hipGetLastError();
     }));
-    for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
-        SrcBatch<T> b{};
-        b.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, src.size() - q));
-        for (int j = 0; j < b.count; ++j) b.idx[j] = src[q + j].first;
+    for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
+        SrcBatch<T> sb{};
+        sb.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, b.src.size() - q));
+        for (int j = 0; j < sb.count; ++j) sb.idx[j] = b.src[q + j].first;
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-            hipLaunchKernelGGL(k_adj_mark_sources<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, b, w.up,
+            hipLaunchKernelGGL(k_adj_mark_sources<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, sb, w.up,
                                static_cast<T*>(w.coef), static_cast<T*>(w.D));
             return hipGetLastError();
         }));
         ++launched;
     }
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
-                  [&] { return launch_zero_words(w.tstamp, 4 * static_cast<size_t>(G.ntiles), s); }));
+                  [&] { return launch_zero_words(w.tstamp, 4 * static_cast<size_t>(b.ntiles), s); }));
     AdjArgs<T> a{};
     a.F = F;
     a.phi = phi;
@@ -425,12 +419,12 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
     }));
     launched += 4;
     auto step = [&](int64_t t) {
-        AdjArgs<T> b = a;
-        b.cur = w.seg[t & 1];
-        b.next = w.seg[(t + 1) & 1];
-        b.tag_slot = static_cast<int>(t & 1);
+        AdjArgs<T> c = a;
+        c.cur = w.seg[t & 1];
+        c.next = w.seg[(t + 1) & 1];
+        c.tag_slot = static_cast<int>(t & 1);
         return timed(prof, EIK_KERNEL_ADJOINT, [&] {
-            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, b, G, inner);
+            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, c, G, inner);
             return hipGetLastError();
         });
     };
@@ -438,8 +432,8 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
     eik_status rc = run_loop(step, [&](int64_t t) { return w.seg[t & 1].count; }, GA, cap, async, s, &nl);
     launched += nl;
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, gd.n, static_cast<const T*>(w.D),
-                           static_cast<const T*>(w.lam), out);
+        hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, static_cast<int>(b.n),
+                           static_cast<const T*>(w.D), static_cast<const T*>(w.lam), out);
         return hipGetLastError();
     }));
     ++launched;
@@ -459,23 +453,21 @@ eik_status adj_run(const GridDims& gd, const T* F, const T* phi, double h,
 
 }  // namespace
 
-size_t adjoint_workspace_bytes(const GridDims& gd, const eik_options& o) {
-    return adj_layout(nullptr, gd, o.dtype == EIK_FLOAT64 ? 8 : 4).bytes;
+size_t adjoint_workspace_bytes(const Batch& b, size_t esz) {
+    return adj_layout(nullptr, with_tiles(b, adj_tile(b.nd)), esz).bytes;
 }
 
 template <typename T>
-eik_status adjoint_solve(const GridDims& gd, const T* F, const T* phi, double h,
-                         const std::vector<std::pair<int, double>>& src, const T* g, T* out,
-                         const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
-    if (gd.nd == 2) return adj_run<T, 2, 32, 32, 1>(gd, F, phi, h, src, g, out, o, ws, s, st);
-    return adj_run<T, 3, 8, 8, 8>(gd, F, phi, h, src, g, out, o, ws, s, st);
+eik_status adjoint_solve(const Batch& b0, const T* F, const T* phi, const T* g, T* out, const eik_options& o,
+                         char* ws, hipStream_t s, eik_stats* st) {
+    const Batch b = with_tiles(b0, adj_tile(b0.nd));
+    if (b.nd == 2) return adj_run<T, 2, 32, 32, 1>(b, F, phi, g, out, o, ws, s, st);
+    return adj_run<T, 3, 8, 8, 8>(b, F, phi, g, out, o, ws, s, st);
 }
 
-template eik_status adjoint_solve<float>(const GridDims&, const float*, const float*, double,
-                                         const std::vector<std::pair<int, double>>&, const float*, float*,
+template eik_status adjoint_solve<float>(const Batch&, const float*, const float*, const float*, float*,
                                          const eik_options&, char*, hipStream_t, eik_stats*);
-template eik_status adjoint_solve<double>(const GridDims&, const double*, const double*, double,
-                                          const std::vector<std::pair<int, double>>&, const double*,
-                                          double*, const eik_options&, char*, hipStream_t, eik_stats*);
+template eik_status adjoint_solve<double>(const Batch&, const double*, const double*, const double*, double*,
+                                          const eik_options&, char*, hipStream_t, eik_stats*);
 
 }  // namespace eik

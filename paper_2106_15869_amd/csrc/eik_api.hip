@@ -130,8 +130,23 @@ static NodeWs node_layout(char* base, int64_t n, size_t esz, bool det, bool fim)
 
 static size_t elem_size(eik_dtype d) { return d == EIK_FLOAT64 ? 8 : 4; }
 
+// A single grid as a batch of one instance (sources may be empty for size
+// queries).
+static Batch single_batch(const Problem& P, const eik_options& o, TileCfg c,
+                          const std::vector<std::pair<int, double>>& src, double h) {
+    Batch b;
+    b.nd = P.g.nd;
+    b.cfg = c;
+    batch_add(b, P.g.nx, P.g.ny, P.g.nz, h);
+    b.src = src;
+    b.src_inst.assign(src.size(), 0);
+    (void)o;
+    return b;
+}
+
 static size_t workspace_bytes(const Problem& P, const eik_options& o) {
-    if (o.variant == EIK_VARIANT_TILE) return tile_workspace_bytes(P.g, o);
+    if (o.variant == EIK_VARIANT_TILE)
+        return tile_workspace_bytes(single_batch(P, o, pick_tile(P.g.nd, o), {}, 1.0), elem_size(o.dtype));
     return node_layout(nullptr, P.n, elem_size(o.dtype), (o.flags & EIK_FLAG_DETERMINISTIC) != 0,
                        o.variant == EIK_VARIANT_FIM).bytes;
 }
@@ -330,11 +345,12 @@ EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, d
     }
     auto src = dedupe_sources(sources, o.source_values, n_sources);
     if (o.variant == EIK_VARIANT_TILE) {
+        const Batch b = single_batch(P, o, pick_tile(P.g.nd, o), src, h);
         if (o.dtype == EIK_FLOAT64)
-            return solve_tile<double>(P.g, static_cast<const double*>(F), h, eps, src,
-                                      static_cast<double*>(phi_out), o, ws, s, o.stats);
-        return solve_tile<float>(P.g, static_cast<const float*>(F), h, eps, src,
-                                 static_cast<float*>(phi_out), o, ws, s, o.stats);
+            return solve_tile<double>(b, static_cast<const double*>(F), eps, static_cast<double*>(phi_out), o, ws,
+                                      s, o.stats);
+        return solve_tile<float>(b, static_cast<const float*>(F), eps, static_cast<float*>(phi_out), o, ws, s,
+                                 o.stats);
     }
     if (o.dtype == EIK_FLOAT64)
         return solve_nodelist<double>(P, static_cast<const double*>(F), h, eps, src,
@@ -373,7 +389,7 @@ EIK_API size_t eik_adjoint_workspace_size(int32_t ndim, const int64_t* dims, con
     if (check_shape(ndim, dims, P) != EIK_OK) return 0;
     eik_options o = resolve(opt);
     if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64) return 0;
-    return adjoint_workspace_bytes(P.g, o);
+    return adjoint_workspace_bytes(single_batch(P, o, pick_tile(P.g.nd, o), {}, 1.0), elem_size(o.dtype));
 }
 
 EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, const int64_t* dims,
@@ -390,7 +406,9 @@ EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, con
         return fail(EIK_ERR_INVALID_ARGUMENT, "dL_dF_out must not alias the inputs");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
     if ((rc = check_sources(P, sources, n_sources, nullptr))) return rc;
-    const size_t need = adjoint_workspace_bytes(P.g, o);
+    auto src = dedupe_sources(sources, nullptr, n_sources);
+    const Batch b = single_batch(P, o, pick_tile(P.g.nd, o), src, h);
+    const size_t need = adjoint_workspace_bytes(b, elem_size(o.dtype));
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     OwnedWs owned;
     char* ws = static_cast<char*>(o.workspace);
@@ -402,14 +420,166 @@ EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, con
         owned.s = s;
         ws = static_cast<char*>(owned.p);
     }
-    auto src = dedupe_sources(sources, nullptr, n_sources);
     if (o.dtype == EIK_FLOAT64)
-        return adjoint_solve<double>(P.g, static_cast<const double*>(F), static_cast<const double*>(phi), h,
-                                     src, static_cast<const double*>(dL_dphi),
-                                     static_cast<double*>(dL_dF_out), o, ws, s, o.stats);
-    return adjoint_solve<float>(P.g, static_cast<const float*>(F), static_cast<const float*>(phi), h, src,
-                                static_cast<const float*>(dL_dphi), static_cast<float*>(dL_dF_out), o, ws,
-                                s, o.stats);
+        return adjoint_solve<double>(b, static_cast<const double*>(F), static_cast<const double*>(phi),
+                                     static_cast<const double*>(dL_dphi), static_cast<double*>(dL_dF_out), o, ws,
+                                     s, o.stats);
+    return adjoint_solve<float>(b, static_cast<const float*>(F), static_cast<const float*>(phi),
+                                static_cast<const float*>(dL_dphi), static_cast<float*>(dL_dF_out), o, ws, s,
+                                o.stats);
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+namespace eik {
+
+// Validate the instance descriptions and sources and build the batch (with
+// empty sources when `sources` is NULL: workspace queries).
+static eik_status make_batch(int32_t ndim, const eik_instance* inst, int32_t n_inst, const int64_t* sources,
+                             const double* values, const eik_options& o, Batch& b) {
+    if (ndim != 2 && ndim != 3) return fail(EIK_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+    if (!inst || n_inst < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "need at least one instance");
+    b = Batch{};
+    b.nd = ndim;
+    b.cfg = pick_tile(ndim, o);
+    std::vector<std::pair<int, int64_t>> ranges;
+    int64_t nsrc = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const eik_instance& e = inst[k];
+        int64_t d[3] = {1, 1, 1};
+        for (int j = 0; j < ndim; ++j) {
+            if (e.dims[j] < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every dim must be >= 1");
+            d[3 - ndim + j] = e.dims[j];
+        }
+        if (!(e.h > 0.0) || !std::isfinite(e.h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+        if (e.n_sources < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every instance needs a source");
+        const int64_t n = d[0] * d[1] * d[2];
+        if (d[0] >= (int64_t(1) << 31) || d[1] >= (int64_t(1) << 31) || d[2] >= (int64_t(1) << 31) ||
+            b.n + n >= (int64_t(1) << 31))
+            return fail(EIK_ERR_INVALID_ARGUMENT, "a batch must have < 2^31 nodes");
+        batch_add(b, static_cast<int>(d[2]), static_cast<int>(d[1]), static_cast<int>(d[0]), e.h);
+        nsrc += e.n_sources;
+    }
+    if (!sources) return EIK_OK;
+    std::vector<int64_t> glob(static_cast<size_t>(nsrc));
+    std::vector<int> owner(static_cast<size_t>(nsrc));
+    int64_t q = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const HostInst& h = b.inst[static_cast<size_t>(k)];
+        const int64_t n = static_cast<int64_t>(h.nx) * h.ny * h.nz;
+        for (int64_t j = 0; j < inst[k].n_sources; ++j, ++q) {
+            if (sources[q] < 0 || sources[q] >= n) return fail(EIK_ERR_INVALID_ARGUMENT, "source index out of range");
+            if (values && !std::isfinite(values[q])) return fail(EIK_ERR_INVALID_ARGUMENT, "source values must be finite");
+            glob[static_cast<size_t>(q)] = h.node_base + sources[q];
+            owner[static_cast<size_t>(q)] = k;
+        }
+    }
+    b.src = dedupe_sources(glob.data(), values, nsrc);
+    // instances own disjoint index ranges: recover each source's owner
+    b.src_inst.resize(b.src.size());
+    for (size_t j = 0; j < b.src.size(); ++j) {
+        int lo = 0, hi = n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.inst[static_cast<size_t>(mid)].node_base <= b.src[j].first) lo = mid; else hi = mid;
+        }
+        b.src_inst[j] = lo;
+    }
+    return EIK_OK;
+}
+
+static eik_status batch_options(const eik_options& o) {
+    eik_status rc = check_options(o);
+    if (rc) return rc;
+    if (o.variant != EIK_VARIANT_TILE)
+        return fail(EIK_ERR_UNSUPPORTED, "batched solves use the tile variant");
+    return EIK_OK;
+}
+
+}  // namespace eik
+
+EIK_API size_t eik_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                                        const eik_options* opt) {
+    eik_options o = resolve(opt);
+    o.flags &= ~static_cast<uint32_t>(EIK_FLAG_ASYNC);
+    o.workspace = nullptr;
+    Batch b;
+    if (batch_options(o) != EIK_OK || make_batch(ndim, inst, n_inst, nullptr, nullptr, o, b) != EIK_OK) return 0;
+    return tile_workspace_bytes(b, elem_size(o.dtype));
+}
+
+EIK_API eik_status eik_solve_batch(const void* F, int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                                   const int64_t* sources, double eps, void* phi_out, const eik_options* opt) {
+    g_last_error.clear();
+    eik_options o = resolve(opt);
+    eik_status rc = batch_options(o);
+    if (rc) return rc;
+    if (!F || !phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "F and phi_out must be non-NULL");
+    if (F == phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_out must not alias F");
+    if (!sources) return fail(EIK_ERR_INVALID_ARGUMENT, "sources is NULL");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(EIK_ERR_INVALID_ARGUMENT, "eps must be finite and >= 0");
+    Batch b;
+    if ((rc = make_batch(ndim, inst, n_inst, sources, o.source_values, o, b))) return rc;
+    const size_t need = tile_workspace_bytes(b, elem_size(o.dtype));
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    OwnedWs owned;
+    char* ws = static_cast<char*>(o.workspace);
+    if (ws) {
+        if (o.workspace_bytes < need) return fail(EIK_ERR_OUT_OF_MEMORY, "workspace too small");
+    } else {
+        if (hipMallocAsync(&owned.p, need, s) != hipSuccess)
+            return fail(EIK_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        owned.s = s;
+        ws = static_cast<char*>(owned.p);
+    }
+    if (o.dtype == EIK_FLOAT64)
+        return solve_tile<double>(b, static_cast<const double*>(F), eps, static_cast<double*>(phi_out), o, ws, s,
+                                  o.stats);
+    return solve_tile<float>(b, static_cast<const float*>(F), eps, static_cast<float*>(phi_out), o, ws, s, o.stats);
+}
+
+EIK_API size_t eik_adjoint_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
+                                                const eik_options* opt) {
+    eik_options o = resolve(opt);
+    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64) return 0;
+    Batch b;
+    if (make_batch(ndim, inst, n_inst, nullptr, nullptr, o, b) != EIK_OK) return 0;
+    return adjoint_workspace_bytes(b, elem_size(o.dtype));
+}
+
+EIK_API eik_status eik_adjoint_batch(const void* F, const void* phi, int32_t ndim, const eik_instance* inst,
+                                     int32_t n_inst, const int64_t* sources, const void* dL_dphi,
+                                     void* dL_dF_out, const eik_options* opt) {
+    g_last_error.clear();
+    eik_options o = resolve(opt);
+    eik_status rc = check_options(o);
+    if (rc) return rc;
+    if (!F || !phi || !dL_dphi || !dL_dF_out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
+    if (dL_dF_out == F || dL_dF_out == phi || dL_dF_out == dL_dphi)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "dL_dF_out must not alias the inputs");
+    if (!sources) return fail(EIK_ERR_INVALID_ARGUMENT, "sources is NULL");
+    Batch b;
+    if ((rc = make_batch(ndim, inst, n_inst, sources, nullptr, o, b))) return rc;
+    const size_t need = adjoint_workspace_bytes(b, elem_size(o.dtype));
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    OwnedWs owned;
+    char* ws = static_cast<char*>(o.workspace);
+    if (ws) {
+        if (o.workspace_bytes < need) return fail(EIK_ERR_OUT_OF_MEMORY, "workspace too small");
+    } else {
+        if (hipMallocAsync(&owned.p, need, s) != hipSuccess)
+            return fail(EIK_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        owned.s = s;
+        ws = static_cast<char*>(owned.p);
+    }
+    if (o.dtype == EIK_FLOAT64)
+        return adjoint_solve<double>(b, static_cast<const double*>(F), static_cast<const double*>(phi),
+                                     static_cast<const double*>(dL_dphi), static_cast<double*>(dL_dF_out), o, ws,
+                                     s, o.stats);
+    return adjoint_solve<float>(b, static_cast<const float*>(F), static_cast<const float*>(phi),
+                                static_cast<const float*>(dL_dphi), static_cast<float*>(dL_dF_out), o, ws, s,
+                                o.stats);
 }
 
 EIK_API const char* eik_status_string(eik_status s) {

@@ -36,7 +36,8 @@ constexpr int kMaxSrcBatch = 64;
 template <typename T>
 struct SrcBatch {
     int count;
-    int idx[kMaxSrcBatch];
+    int idx[kMaxSrcBatch];    // flat index in the batch-wide arrays
+    int inst[kMaxSrcBatch];   // instance of the source (batched tile solves)
     T val[kMaxSrcBatch];
 };
 
@@ -73,6 +74,35 @@ struct GridDims {
     int nx, ny, nz;
     int n;
 };
+
+// One grid of a batch (a single solve is a batch of one): its extents, its
+// tile grid and where its nodes and tiles start in the batch-wide arrays.
+template <typename T>
+struct Inst {
+    int nx, ny, nz;
+    int ntx, nty, ntz;
+    int node_base;   // flat index of the grid's first node in F / phi / labels
+    int tile_base;   // id of its first tile
+    T h;
+};
+
+// Batch-wide tile geometry handed to every tile kernel.
+template <typename T>
+struct BatchGeom {
+    Inst<T> one;              // the instance when ninst == 1
+    const Inst<T>* table;     // device, ninst entries (used when ninst > 1)
+    const int* tile_inst;     // device, instance of every tile (ninst > 1)
+    int ninst;
+    int ntiles;               // over all instances
+};
+
+// Instance holding tile t (t must be uniform across the wave).
+template <typename T>
+__device__ __forceinline__ Inst<T> inst_of(const BatchGeom<T>& g, int t) {
+    if (g.ninst == 1) return g.one;
+    const int k = __builtin_amdgcn_readfirstlane(g.tile_inst[__builtin_amdgcn_readfirstlane(t)]);
+    return g.table[k];
+}
 
 // ---- launchers implemented in eik_nodelist.hip (T = float/double, ND = 2/3)
 template <typename T>

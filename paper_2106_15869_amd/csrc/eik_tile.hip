@@ -31,6 +31,7 @@
 #include "eik_device.hpp"
 #include "eik_host.hpp"
 #include "eik_seglist.hpp"
+#include "eik_batch.hpp"
 #include "eik_tile.hpp"
 
 namespace eik {
@@ -48,11 +49,6 @@ constexpr int kPad = 32;      // ints between counters (separate cache lines)
 // Dirty-face mask bit meaning "recheck every node of the tile".
 constexpr uint32_t kAllFaces = 64u;
 
-struct TileGeom {
-    int nx, ny, nz;   // grid
-    int ntx, nty, ntz;
-    int ntiles;
-};
 
 // A tile list: kSub sub-lists of `cap` tile ids.  count[k * kPad] is the
 // length of sub-list k (appended with atomicAdd by producers), fetch[k * kPad]
@@ -120,7 +116,7 @@ struct Owned {
 // Stage the tile and its halo: values (+inf outside) and labels (kOut outside).
 // All global loads of a lane are issued before its first LDS store.
 template <typename T, int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ void stage(const TileGeom& g, int x0, int y0, int z0, const T* phi,
+__device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, const T* phi,
                                       const uint8_t* lab, T* sphi, uint8_t* sl) {
     using S = Shape<ND, TX, TY, TZ>;
     constexpr int NIT = (S::NL + kBlock - 1) / kBlock;
@@ -135,7 +131,7 @@ __device__ __forceinline__ void stage(const TileGeom& g, int x0, int y0, int z0,
         const int lz = q / (S::LX * S::LY);
         const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
         const bool in = q < S::NL && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-        const int G = (gz * g.ny + gy) * g.nx + gx;
+        const int G = g.node_base + (gz * g.ny + gy) * g.nx + gx;
         v[j] = in ? phi[G] : inf;
         l[j] = in ? lab[G] : kOut;
     }
@@ -150,7 +146,7 @@ __device__ __forceinline__ void stage(const TileGeom& g, int x0, int y0, int z0,
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ void own_nodes(const TileGeom& g, int x0, int y0, int z0, const T* F, T h,
+__device__ __forceinline__ void own_nodes(const Inst<T>& g, int x0, int y0, int z0, const T* F,
                                           Owned<T, Shape<ND, TX, TY, TZ>::NPT>& o) {
     using S = Shape<ND, TX, TY, TZ>;
 #pragma unroll
@@ -159,7 +155,7 @@ __device__ __forceinline__ void own_nodes(const TileGeom& g, int x0, int y0, int
         const int x = n % TX, y = (n / TX) % TY, z = ND == 3 ? n / (TX * TY) : 0;
         const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
         o.ok[r] = n < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
-        o.G[r] = (gz * g.ny + gy) * g.nx + gx;
+        o.G[r] = g.node_base + (gz * g.ny + gy) * g.nx + gx;
         o.L[r] = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
         int e = 0;
         if (x == 0) e |= 1;
@@ -182,7 +178,7 @@ __device__ __forceinline__ void own_nodes(const TileGeom& g, int x0, int y0, int
         }
         o.face[r] = f;
         o.H[r] = pos_inf<T>();
-        if (o.ok[r]) o.H[r] = cell_H(h, F[o.G[r]]);
+        if (o.ok[r]) o.H[r] = cell_H(g.h, F[o.G[r]]);
     }
 }
 
@@ -210,7 +206,8 @@ __device__ __forceinline__ int lds_offset(int d) {
     }
 }
 
-__device__ __forceinline__ int neighbour_tile(const TileGeom& g, int t, int d) {
+template <typename T>
+__device__ __forceinline__ int neighbour_tile(const Inst<T>& g, int t, int d) {
     switch (d) {
         case 0: return t - 1;
         case 1: return t + 1;
@@ -325,8 +322,8 @@ __device__ __forceinline__ int edge_bits(int x, int y, int z) {
 }
 
 // bit d: the grid continues past the tile face in direction d
-template <int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ int open_bits(const TileGeom& g, int x0, int y0, int z0) {
+template <int ND, int TX, int TY, int TZ, typename T>
+__device__ __forceinline__ int open_bits(const Inst<T>& g, int x0, int y0, int z0) {
     int f = (x0 > 0 ? 1 : 0) | (x0 + TX < g.nx ? 2 : 0) | (y0 > 0 ? 4 : 0) | (y0 + TY < g.ny ? 8 : 0);
     if (ND == 3) f |= (z0 > 0 ? 16 : 0) | (z0 + TZ < g.nz ? 32 : 0);
     return f;
@@ -351,8 +348,7 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 // STEP 2 on tiles
 // ---------------------------------------------------------------------------
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom g, T h, T eps,
-                                                        int inner) {
+__global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
@@ -375,7 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
         const int t = list_fetch(a.cur, k, len, &s_slot);
         if (t < 0) break;
         ++visits;
-        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
@@ -387,9 +385,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
             int x, y, z;
             node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
             ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-            G[r] = ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+            G[r] = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
             if (nn < S::NT) {
-                sH[nn] = ok[r] ? cell_H(h, a.F[G[r]]) : inf;
+                sH[nn] = ok[r] ? cell_H(g.h, a.F[G[r]]) : inf;
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
             }
@@ -523,17 +521,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, TileGeom 
 // STEP 3: whole-grid detection, one workgroup per tile
 // ---------------------------------------------------------------------------
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom g, T h, T eps) {
+__global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom<T> bg, T eps) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
     const uint32_t ntag = launch_tag(a);
-    for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
-        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    for (int t = blockIdx.x; t < bg.ntiles; t += gridDim.x) {
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         Owned<T, S::NPT> o;
-        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, h, o);
+        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, o);
         __syncthreads();
         bool flag = false;
 #pragma unroll
@@ -558,8 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, TileGeom 
 // update cannot change: the node is not upwind of them), and a face neighbour
 // below the halo value marks that face dirty in the tile across it.
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom g, T h, T eps,
-                                                        int inner) {
+__global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
@@ -582,7 +581,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
         const int t = list_fetch(a.cur, k, len, &s_slot);
         if (t < 0) break;
         ++visits;
-        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         uint32_t mask_in = 0;
@@ -601,9 +602,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
             node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
             E[r] = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
             ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-            G[r] = ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+            G[r] = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
             if (nn < S::NT) {
-                sH[nn] = ok[r] ? cell_H(h, a.F[G[r]]) : inf;
+                sH[nn] = ok[r] ? cell_H(g.h, a.F[G[r]]) : inf;
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
             }
@@ -717,17 +718,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, TileGeom 
 // Initial tile list: tiles holding a grid neighbour of a source (claimed with
 // tag 1).
 template <typename T>
-__global__ void k_seed_tiles(TileGeom g, int nd, int tx_, int ty_, int tz_, SrcBatch<T> b,
+__global__ void k_seed_tiles(BatchGeom<T> bg, int nd, int tx_, int ty_, int tz_, SrcBatch<T> b,
                              uint32_t* tstamp, TList out) {
     const int k = threadIdx.x;
     if (k >= b.count) return;
-    const int i = b.idx[k];
+    const Inst<T> g = bg.ninst == 1 ? bg.one : bg.table[b.inst[k]];
+    const int i = b.idx[k] - g.node_base;
     const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
     const int dx[6] = {-1, 1, 0, 0, 0, 0}, dy[6] = {0, 0, -1, 1, 0, 0}, dz[6] = {0, 0, 0, 0, -1, 1};
     for (int d = 0; d < 2 * nd; ++d) {
         const int X = x + dx[d], Y = y + dy[d], Z = z + dz[d];
         if (X < 0 || X >= g.nx || Y < 0 || Y >= g.ny || Z < 0 || Z >= g.nz) continue;
-        push_tile(out, tstamp, ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_), 1u);
+        push_tile(out, tstamp, g.tile_base + ((Z / tz_) * g.nty + (Y / ty_)) * g.ntx + (X / tx_), 1u);
     }
 }
 
@@ -745,33 +747,6 @@ __global__ void k_seed_all_tiles(int ntiles, uint32_t* tstamp, TList out) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-struct TileCfg {
-    int tx, ty, tz;
-};
-
-TileCfg pick_tile(const GridDims& gd, const eik_options& o) {
-    TileCfg c{o.tile[2], o.tile[1], o.tile[0]};
-    if (gd.nd == 2) {
-        c.tz = 1;
-        if (c.tx == 0 || c.ty == 0) c = TileCfg{32, 32, 1};
-    } else if (c.tx == 0 || c.ty == 0 || c.tz == 0) {
-        c = TileCfg{8, 8, 8};
-    }
-    return c;
-}
-
-TileGeom make_geom(const GridDims& gd, const TileCfg& c) {
-    TileGeom g;
-    g.nx = gd.nx;
-    g.ny = gd.ny;
-    g.nz = gd.nz;
-    g.ntx = (gd.nx + c.tx - 1) / c.tx;
-    g.nty = (gd.ny + c.ty - 1) / c.ty;
-    g.ntz = (gd.nz + c.tz - 1) / c.tz;
-    g.ntiles = g.ntx * g.nty * g.ntz;
-    return g;
-}
-
 struct TileWs {
     Ctl* ctl;
     unsigned long long* blkstat;
@@ -780,6 +755,8 @@ struct TileWs {
     uint32_t* tmask;    // two arrays of ntiles dirty-face masks (by launch parity)
     int* data[2];       // two list buffers (alternating)
     int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}
+    void* table;        // instance table (batches of more than one instance)
+    int* tile_inst;     // instance of every tile (idem)
     int cap;
     size_t bytes;
     int* count_of(int set) const { return counters + set * 2 * kSub * kPad; }
@@ -789,7 +766,7 @@ struct TileWs {
 constexpr size_t kCounterBytes = 3 * 2 * kSub * kPad * sizeof(int);
 
 // A sub-list can receive every tile (tiles are deduplicated per list).
-TileWs tile_layout(char* base, int64_t n, int ntiles) {
+TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t inst_bytes) {
     TileWs w{};
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -797,7 +774,7 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
         off = align_up(off + b, 256);
         return p;
     };
-    w.cap = ntiles + 64;
+    w.cap = static_cast<int>(ntiles + 64);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
@@ -805,36 +782,35 @@ TileWs tile_layout(char* base, int64_t n, int ntiles) {
     w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
     w.counters = reinterpret_cast<int*>(take(kCounterBytes));
     for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
+    if (ninst > 1) {
+        w.table = take(inst_bytes * ninst);
+        w.tile_inst = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
+    }
     w.bytes = off;
     return w;
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
 struct TileKernels {
-    static hipError_t update(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner,
-                             hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
-                           eps, inner);
+    static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
-    static hipError_t detect(const TileIter<T>& a, const TileGeom& g, T h, T eps, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
-                           eps);
+    static hipError_t detect(const TileIter<T>& a, const BatchGeom<T>& g, T eps, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps);
         return hipGetLastError();
     }
-    static hipError_t remedy(const TileIter<T>& a, const TileGeom& g, T h, T eps, int inner,
-                             hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, h,
-                           eps, inner);
+    static hipError_t remedy(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
 };
 
 template <typename T>
 struct TileOps {
-    hipError_t (*update)(const TileIter<T>&, const TileGeom&, T, T, int, hipStream_t) = nullptr;
-    hipError_t (*detect)(const TileIter<T>&, const TileGeom&, T, T, hipStream_t) = nullptr;
-    hipError_t (*remedy)(const TileIter<T>&, const TileGeom&, T, T, int, hipStream_t) = nullptr;
+    hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
+    hipError_t (*detect)(const TileIter<T>&, const BatchGeom<T>&, T, hipStream_t) = nullptr;
+    hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
 };
 
 template <typename T, int ND, int TX, int TY, int TZ>
@@ -867,50 +843,88 @@ bool select_ops(int nd, const TileCfg& c, TileOps<T>& k) {
 
 }  // namespace
 
-size_t tile_workspace_bytes(const GridDims& gd, const eik_options& o) {
-    TileCfg c = pick_tile(gd, o);
-    TileGeom g = make_geom(gd, c);
-    return tile_layout(nullptr, gd.n, g.ntiles).bytes;
+TileCfg pick_tile(int nd, const eik_options& o) {
+    TileCfg c{o.tile[2], o.tile[1], o.tile[0]};
+    if (nd == 2) {
+        c.tz = 1;
+        if (c.tx == 0 || c.ty == 0) c = TileCfg{32, 32, 1};
+    } else if (c.tx == 0 || c.ty == 0 || c.tz == 0) {
+        c = TileCfg{8, 8, 8};
+    }
+    return c;
+}
+
+void batch_add(Batch& b, int nx, int ny, int nz, double h) {
+    HostInst e;
+    e.nx = nx;
+    e.ny = ny;
+    e.nz = nz;
+    e.ntx = (nx + b.cfg.tx - 1) / b.cfg.tx;
+    e.nty = (ny + b.cfg.ty - 1) / b.cfg.ty;
+    e.ntz = (nz + b.cfg.tz - 1) / b.cfg.tz;
+    e.node_base = static_cast<int>(b.n);
+    e.tile_base = static_cast<int>(b.ntiles);
+    e.h = h;
+    b.inst.push_back(e);
+    b.n += static_cast<int64_t>(nx) * ny * nz;
+    b.ntiles += static_cast<int64_t>(e.ntx) * e.nty * e.ntz;
+}
+
+Batch with_tiles(const Batch& b, const TileCfg& c) {
+    Batch r;
+    r.nd = b.nd;
+    r.cfg = c;
+    for (const HostInst& e : b.inst) batch_add(r, e.nx, e.ny, e.nz, e.h);
+    r.src = b.src;
+    r.src_inst = b.src_inst;
+    return r;
+}
+
+size_t tile_workspace_bytes(const Batch& b, size_t esz) {
+    const size_t ib = esz == 8 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+    return tile_layout(nullptr, b.n, b.ntiles, b.inst.size(), ib).bytes;
 }
 
 template <typename T>
-eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
-                      const std::vector<std::pair<int, double>>& src, T* phi, const eik_options& o,
-                      char* ws, hipStream_t s, eik_stats* st) {
+eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_options& o, char* ws,
+                      hipStream_t s, eik_stats* st) {
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
-    TileCfg c = pick_tile(gd, o);
+    const TileCfg c = b.cfg;
     TileOps<T> k;
-    if (!select_ops<T>(gd.nd, c, k)) return fail(EIK_ERR_INVALID_ARGUMENT, "unsupported tile shape");
-    TileGeom g = make_geom(gd, c);
-    TileWs w = tile_layout(ws, gd.n, g.ntiles);
-    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * static_cast<int64_t>(gd.n) + 64;
+    if (!select_ops<T>(b.nd, c, k)) return fail(EIK_ERR_INVALID_ARGUMENT, "unsupported tile shape");
+    TileWs w = tile_layout(ws, b.n, b.ntiles, b.inst.size(), sizeof(Inst<T>));
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * b.n + 64;
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
+    const int ntiles = static_cast<int>(b.ntiles);
     int64_t launched = 0;
 
     Profiler prof;
     prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
     const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks;
+    BatchGeom<T> geom;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return upload_batch_geom<T>(b, w.table, w.tile_inst, s, geom, launched); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, gd.n, w.ctl, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, static_cast<int>(b.n), w.ctl, s); }));
     // tile stamps and dirty-face masks are adjacent: clear both
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + 2 * static_cast<size_t>(g.ntiles)), s);
+        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + 2 * static_cast<size_t>(ntiles)), s);
     }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
     launched += 5;
     std::vector<SrcBatch<T>> batches;
-    for (size_t q = 0; q < src.size(); q += kMaxSrcBatch) {
-        SrcBatch<T> b{};
-        b.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, src.size() - q));
-        for (int j = 0; j < b.count; ++j) {
-            b.idx[j] = src[q + j].first;
-            b.val[j] = static_cast<T>(src[q + j].second);
+    for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
+        SrcBatch<T> sb{};
+        sb.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, b.src.size() - q));
+        for (int j = 0; j < sb.count; ++j) {
+            sb.idx[j] = b.src[q + j].first;
+            sb.inst[j] = b.src_inst[q + j];
+            sb.val[j] = static_cast<T>(b.src[q + j].second);
         }
-        batches.push_back(b);
+        batches.push_back(sb);
     }
-    for (auto& b : batches)
-        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, b, s); }));
+    for (auto& sb : batches)
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, sb, s); }));
     launched += static_cast<int64_t>(batches.size());
     auto list_of = [&](int64_t t) {
         TList L;
@@ -920,21 +934,26 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         L.cap = w.cap;
         return L;
     };
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        if (batches.size() == 1) {
-            // tiles next to the sources
-            hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, g, gd.nd, c.tx, c.ty, c.tz,
-                               batches[0], w.tstamp, list_of(0));
-        } else {
-            // many sources: start from every tile; tiles with nothing to do drop out
-            hipLaunchKernelGGL(k_seed_all_tiles, dim3(std::min((g.ntiles + kBlock - 1) / kBlock, 1024)),
-                               dim3(kBlock), 0, s, g.ntiles, w.tstamp, list_of(0));
-        }
-        return hipGetLastError();
-    }));
-    launched += 1;
+    if (batches.size() <= 8) {
+        // tiles next to the sources
+        for (auto& sb : batches)
+            HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+                hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, geom, b.nd, c.tx, c.ty, c.tz,
+                                   sb, w.tstamp, list_of(0));
+                return hipGetLastError();
+            }));
+        launched += static_cast<int64_t>(batches.size());
+    } else {
+        // many sources: start from every tile; tiles with nothing to do drop out
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+            hipLaunchKernelGGL(k_seed_all_tiles, dim3(std::min((ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock),
+                               0, s, ntiles, w.tstamp, list_of(0));
+            return hipGetLastError();
+        }));
+        launched += 1;
+    }
 
-    const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
+    const T eT = static_cast<T>(eps);
     int64_t gl = 0;  // launches in the tag chain so far (selects the tag slot)
     // launch t drains list t and fills list t + 1; lists alternate two buffers
     // and three counter sets (the set of list t + 2 is cleared by launch t)
@@ -944,8 +963,8 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         a.phi = phi;
         a.lab = w.lab;
         a.tstamp = w.tstamp;
-        a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * g.ntiles;
-        a.mask_next = w.tmask + static_cast<size_t>((t + 1) & 1) * g.ntiles;
+        a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * ntiles;
+        a.mask_next = w.tmask + static_cast<size_t>((t + 1) & 1) * ntiles;
         a.cur = list_of(t);
         a.next = list_of(t + 1);
         a.zero_count = w.count_of(static_cast<int>((t + 2) % 3));
@@ -962,7 +981,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     int64_t n2 = 0;
     eik_status rc = run_loop(
         [&](int64_t t) {
-            return timed(prof, EIK_KERNEL_UPDATE, [&] { return k.update(iter_args(t, 0), g, hT, eT, inner, s); });
+            return timed(prof, EIK_KERNEL_UPDATE, [&] { return k.update(iter_args(t, 0), geom, eT, inner, s); });
         },
         counts, kSub * kPad, cap, async, s, &n2);
     gl += n2;
@@ -975,14 +994,13 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         d.mask_next = w.tmask;  // read by remedy launch 0
         d.first = 0;
         d.tag_slot = static_cast<int>(gl & 1);
-        HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, g, hT, eT, s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, geom, eT, s); }));
         gl += 1;
         launched += 2;
         int64_t n3 = 0;
         rc = run_loop(
             [&](int64_t t) {
-                return timed(prof, EIK_KERNEL_REMEDY,
-                             [&] { return k.remedy(iter_args(t, 1), g, hT, eT, inner, s); });
+                return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(iter_args(t, 1), geom, eT, inner, s); });
             },
             counts, kSub * kPad, cap, async, s, &n3);
         launched += n3;
@@ -998,7 +1016,7 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
         st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
         st->evals_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS2, kMaxStatBlocks));
-        st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : gd.n - static_cast<int64_t>(src.size());
+        st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : b.n - static_cast<int64_t>(b.src.size());
         st->evals_remedy = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS3, kMaxStatBlocks));
         st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
         st->max_active = static_cast<int64_t>(hs.ctl->max_active);
@@ -1014,11 +1032,9 @@ eik_status solve_tile(const GridDims& gd, const T* F, double h, double eps,
     return rc;
 }
 
-template eik_status solve_tile<float>(const GridDims&, const float*, double, double,
-                                      const std::vector<std::pair<int, double>>&, float*,
-                                      const eik_options&, char*, hipStream_t, eik_stats*);
-template eik_status solve_tile<double>(const GridDims&, const double*, double, double,
-                                       const std::vector<std::pair<int, double>>&, double*,
-                                       const eik_options&, char*, hipStream_t, eik_stats*);
+template eik_status solve_tile<float>(const Batch&, const float*, double, float*, const eik_options&, char*,
+                                      hipStream_t, eik_stats*);
+template eik_status solve_tile<double>(const Batch&, const double*, double, double*, const eik_options&, char*,
+                                       hipStream_t, eik_stats*);
 
 }  // namespace eik

@@ -177,3 +177,63 @@ def test_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         eik.solve(torch.ones(4, 4), 1.0, [0])
+
+
+def _inst(shapes, h=1.0, nsrc=1):
+    arr = (eik.EikInstance * len(shapes))()
+    for k, sh in enumerate(shapes):
+        for j, v in enumerate(sh):
+            arr[k].dims[j] = v
+        arr[k].h = h
+        arr[k].n_sources = nsrc
+    return arr
+
+
+def test_batch_workspace_size(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "tile")
+    one = lib.eik_batch_workspace_size(2, _inst([(64, 64)]), 1, ctypes.byref(o))
+    assert one == eik.eik_workspace_size((64, 64), o)
+    many = lib.eik_batch_workspace_size(2, _inst([(64, 64), (30, 70), (1, 9)]), 3, ctypes.byref(o))
+    assert many > one
+    assert lib.eik_batch_workspace_size(2, _inst([(64, 0)]), 1, ctypes.byref(o)) == 0
+    assert lib.eik_batch_workspace_size(4, _inst([(4, 4)]), 1, ctypes.byref(o)) == 0
+    assert lib.eik_adjoint_batch_workspace_size(3, _inst([(8, 9, 10), (3, 3, 3)]), 2, ctypes.byref(o)) > 0
+    node = eik.make_options(eik.EIK_FLOAT32, "node")
+    assert lib.eik_batch_workspace_size(2, _inst([(8, 8)]), 1, ctypes.byref(node)) == 0
+
+
+@pytest.mark.parametrize("case,why", [
+    ("no_instances", "instance"),
+    ("bad_dim", "dim"),
+    ("bad_h", "h"),
+    ("no_source", "source"),
+    ("source_range", "range"),
+    ("null_sources", "null"),
+])
+def test_batch_invalid_arguments(lib, case, why):
+    shapes = [(8, 8), (5, 7)]
+    inst = _inst(shapes)
+    src = np.array([0, 34], dtype=np.int64)
+    n = len(shapes)
+    if case == "no_instances":
+        n = 0
+    elif case == "bad_dim":
+        inst[1].dims[0] = 0
+    elif case == "bad_h":
+        inst[0].h = float("nan")
+    elif case == "no_source":
+        inst[1].n_sources = 0
+    elif case == "source_range":
+        src[1] = 35  # 5 x 7 grid has 35 nodes
+    o = eik.make_options(eik.EIK_FLOAT32, "tile")
+    sp = None if case == "null_sources" else src.ctypes.data
+    rc = lib.eik_solve_batch(0x1000, 2, inst, n, sp, 0.0, 0x2000, ctypes.byref(o))
+    assert rc == eik.EIK_ERR_INVALID_ARGUMENT
+    assert why in lib.eik_last_error().decode().lower()
+
+
+def test_batch_needs_tile_variant(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "node")
+    src = np.array([0], dtype=np.int64)
+    rc = lib.eik_solve_batch(0x1000, 2, _inst([(8, 8)]), 1, src.ctypes.data, 0.0, 0x2000, ctypes.byref(o))
+    assert rc == eik.EIK_ERR_UNSUPPORTED
