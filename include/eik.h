@@ -230,6 +230,34 @@ eik_status eik_adjoint_batch(const void* F, const void* phi, int32_t ndim, const
 size_t eik_adjoint_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
                                         const eik_options* opt);
 
+/* One candidate configuration timed by eik_tune. */
+typedef struct {
+    int32_t tile[3];      /* (z, y, x) */
+    int32_t inner_iters;  /* inner iterations per tile visit */
+    double ms;            /* best device time of a solve (HIP events) */
+} eik_tune_entry;
+
+/*
+ * eik_tune -- choose the tile shape and inner-iteration cap of the tile
+ * variant for a problem by timing candidate configurations on it (each
+ * solved once to warm up, then timed; device time from HIP events on
+ * opt->stream).  Not in the paper: its run times depend on the GPU's
+ * work-group size, and the tile shape plays that role here.
+ *   F, ndim, dims, h, sources, n_sources, eps  as eik_solve
+ *   phi_scratch  device, N elements; overwritten by the timed solves
+ *   opt          in: dtype, stream, workspace (used when large enough, else
+ *                the library allocates); out: tile and inner_iters of the
+ *                fastest candidate, variant = EIK_VARIANT_TILE
+ *   report       host, nullable: up to report_cap timed candidates;
+ *                *n_report (nullable) receives the count written
+ * The choice is cached per (ndim, dtype, log2 of N) for the life of the
+ * process: a later call for the same class times nothing and reports 0
+ * entries.  Errors as eik_solve.
+ */
+eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                    int64_t n_sources, double eps, void* phi_scratch, eik_options* opt,
+                    eik_tune_entry* report, int32_t report_cap, int32_t* n_report);
+
 /* Human-readable name of a status code (static storage). */
 const char* eik_status_string(eik_status s);
 

@@ -54,7 +54,7 @@ VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
            "eik_adjoint", "eik_adjoint_workspace_size", "eik_status_string", "eik_last_error",
            "eik_abi_version", "eik_solve_batch", "eik_batch_workspace_size", "eik_adjoint_batch",
-           "eik_adjoint_batch_workspace_size")
+           "eik_adjoint_batch_workspace_size", "eik_tune")
 
 
 KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
@@ -63,6 +63,11 @@ KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
 class EikInstance(ctypes.Structure):
     """eik_instance: one grid of a batch."""
     _fields_ = [("dims", ctypes.c_int64 * 3), ("h", ctypes.c_double), ("n_sources", ctypes.c_int64)]
+
+
+class EikTuneEntry(ctypes.Structure):
+    """eik_tune_entry: one timed candidate."""
+    _fields_ = [("tile", ctypes.c_int32 * 3), ("inner_iters", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class EikStats(ctypes.Structure):
@@ -141,6 +146,9 @@ def _load():
     lib.eik_last_error.argtypes = []
     lib.eik_abi_version.restype = i32
     lib.eik_abi_version.argtypes = []
+    lib.eik_tune.restype = ctypes.c_int
+    lib.eik_tune.argtypes = [P, i32, P, d, P, i64, d, P, OP, ctypes.POINTER(EikTuneEntry), i32,
+                             ctypes.POINTER(i32)]
     IP = ctypes.POINTER(EikInstance)
     lib.eik_solve_batch.restype = ctypes.c_int
     lib.eik_solve_batch.argtypes = [P, i32, IP, i32, P, d, P, OP]
@@ -481,6 +489,33 @@ def adjoint_batch(F, phi, shapes, h, sources, dL_dphi, *, out=None, workspace=No
                                        dL_dphi.data_ptr(), res.data_ptr(), ctypes.byref(opt))
     _check(rc)
     return (res, st.to_dict()) if stats else res
+
+
+def tune(F, h: float, sources, eps: float = 0.0, *, stream=None, workspace=None):
+    """Time the tile-variant candidates on this problem (eik_tune) and return
+    {"tile": (z, y, x), "inner_iters": k, "candidates": [...]} -- pass tile and
+    inner_iters to solve().  Cached per (ndim, dtype, log2 N) for the process;
+    a cached answer reports no candidates."""
+    torch = _torch()
+    _check_device_tensor(F, "F")
+    opt = make_options(_dtype_code(F))
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel()
+    dims = _dims(F.shape)
+    src = _sources_array(sources, F.shape)
+    scratch = torch.empty_like(F)
+    rep = (EikTuneEntry * 16)()
+    nrep = ctypes.c_int32(0)
+    with torch.cuda.device(F.device):
+        rc = _load().eik_tune(F.data_ptr(), F.dim(), _np_ptr(dims), float(h), _np_ptr(src), len(src), float(eps),
+                              scratch.data_ptr(), ctypes.byref(opt), rep, 16, ctypes.byref(nrep))
+    _check(rc)
+    cands = [{"tile": tuple(int(v) for v in rep[k].tile), "inner_iters": int(rep[k].inner_iters),
+              "ms": float(rep[k].ms)} for k in range(nrep.value)]
+    return {"tile": tuple(int(v) for v in opt.tile), "inner_iters": int(opt.inner_iters), "candidates": cands}
 
 
 def _make_eikonal_fn():

@@ -1,0 +1,149 @@
+// eik_tune: per-problem choice of the tile shape and inner-iteration cap of
+// the tile variant, by timing candidates with HIP events on the caller's
+// stream.  Choices are cached per (ndim, dtype, log2 N) for the process.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/eik.h"
+#include "eik_host.hpp"
+
+#define EIK_API extern "C" __attribute__((visibility("default")))
+
+namespace eik {
+namespace {
+
+struct Choice {
+    int32_t tile[3];
+    int32_t inner;
+};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Choice>& tune_cache() {
+    static std::map<std::tuple<int, int, int>, Choice> m;
+    return m;
+}
+
+std::vector<Choice> candidates(int nd) {
+    if (nd == 2)
+        return {{{1, 32, 32}, 0}, {{1, 32, 32}, 32}, {{1, 16, 16}, 0}, {{1, 16, 64}, 0},
+                {{1, 8, 32}, 0},  {{1, 64, 64}, 0}};
+    return {{{8, 8, 8}, 0}, {{8, 8, 8}, 32}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+struct Scratch {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    ~Scratch() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+};
+
+}  // namespace
+}  // namespace eik
+
+using namespace eik;
+
+EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                            int64_t n_sources, double eps, void* phi_scratch, eik_options* opt,
+                            eik_tune_entry* report, int32_t report_cap, int32_t* n_report) {
+    g_last_error.clear();
+    if (n_report) *n_report = 0;
+    if (!opt) return fail(EIK_ERR_INVALID_ARGUMENT, "opt is NULL (it receives the choice)");
+    if (!phi_scratch) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_scratch is NULL");
+    if ((ndim != 2 && ndim != 3) || !dims) return fail(EIK_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+    if (opt->flags & (EIK_FLAG_ASYNC | EIK_FLAG_PROFILE))
+        return fail(EIK_ERR_INVALID_ARGUMENT, "eik_tune runs synchronous, unprofiled solves");
+    int64_t n = 1;
+    for (int k = 0; k < ndim; ++k) n *= dims[k] > 0 ? dims[k] : 0;
+    if (n < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every dim must be >= 1");
+    const auto key = std::make_tuple(static_cast<int>(ndim), static_cast<int>(opt->dtype),
+                                     static_cast<int>(std::floor(std::log2(static_cast<double>(n)))));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            opt->variant = EIK_VARIANT_TILE;
+            std::memcpy(opt->tile, it->second.tile, sizeof(opt->tile));
+            opt->inner_iters = it->second.inner;
+            return EIK_OK;
+        }
+    }
+    eik_options base = *opt;
+    base.variant = EIK_VARIANT_TILE;
+    base.stats = nullptr;
+    const std::vector<Choice> cand = candidates(ndim);
+    size_t need = 0;
+    for (const Choice& c : cand) {
+        eik_options q = base;
+        std::memcpy(q.tile, c.tile, sizeof(q.tile));
+        q.workspace = nullptr;
+        need = std::max(need, eik_workspace_size(ndim, dims, &q));
+    }
+    if (need == 0) return fail(EIK_ERR_INVALID_ARGUMENT, "invalid shape or options");
+    hipStream_t s = static_cast<hipStream_t>(base.stream);
+    Scratch scratch;
+    if (!base.workspace || base.workspace_bytes < need) {
+        if (hipMallocAsync(&scratch.p, need, s) != hipSuccess)
+            return fail(EIK_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        scratch.s = s;
+        base.workspace = scratch.p;
+        base.workspace_bytes = need;
+    }
+    Events ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    double best = 0.0;
+    Choice pick = cand[0];
+    int32_t written = 0;
+    for (const Choice& c : cand) {
+        eik_options q = base;
+        std::memcpy(q.tile, c.tile, sizeof(q.tile));
+        q.inner_iters = c.inner;
+        eik_status rc = eik_solve(F, ndim, dims, h, sources, n_sources, eps, phi_scratch, &q);  // warm-up
+        if (rc != EIK_OK) return rc;
+        double ms_best = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipEventRecord(ev.a, s));
+            rc = eik_solve(F, ndim, dims, h, sources, n_sources, eps, phi_scratch, &q);
+            if (rc != EIK_OK) return rc;
+            HIP_TRY(hipEventRecord(ev.b, s));
+            HIP_TRY(hipEventSynchronize(ev.b));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (rep == 0 || ms < ms_best) ms_best = ms;
+        }
+        if (report && written < report_cap) {
+            eik_tune_entry& e = report[written++];
+            std::memcpy(e.tile, c.tile, sizeof(e.tile));
+            e.inner_iters = c.inner;
+            e.ms = ms_best;
+        }
+        if (best == 0.0 || ms_best < best) {
+            best = ms_best;
+            pick = c;
+        }
+    }
+    if (n_report) *n_report = written;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache()[key] = pick;
+    }
+    opt->variant = EIK_VARIANT_TILE;
+    std::memcpy(opt->tile, pick.tile, sizeof(opt->tile));
+    opt->inner_iters = pick.inner;
+    return EIK_OK;
+}

@@ -237,3 +237,18 @@ def test_batch_needs_tile_variant(lib):
     src = np.array([0], dtype=np.int64)
     rc = lib.eik_solve_batch(0x1000, 2, _inst([(8, 8)]), 1, src.ctypes.data, 0.0, 0x2000, ctypes.byref(o))
     assert rc == eik.EIK_ERR_UNSUPPORTED
+
+
+def test_tune_validation(lib):
+    d = np.asarray((16, 16), dtype=np.int64)
+    s = np.asarray([0], dtype=np.int64)
+    n = ctypes.c_int32(-1)
+    assert lib.eik_tune(0x1000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0.0, 0x2000, None, None, 0,
+                        ctypes.byref(n)) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert n.value == 0
+    o = eik.make_options(eik.EIK_FLOAT32, "tile", async_=True)
+    assert lib.eik_tune(0x1000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0.0, 0x2000, ctypes.byref(o), None, 0,
+                        None) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "tile")
+    assert lib.eik_tune(0x1000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0.0, None, ctypes.byref(o), None, 0,
+                        None) == eik.EIK_ERR_INVALID_ARGUMENT

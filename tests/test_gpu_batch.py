@@ -137,3 +137,18 @@ def test_graph_capture_replays(variant):
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         assert np.max(np.abs(got - ref)) <= 1e-12 * ref.max(), (rep, float(junk))
+
+
+@pytest.mark.parametrize("P", [W.lognormal_2d(300, seed=4), W.maze_3d(48)], ids=lambda P: P.name)
+def test_tune_picks_a_candidate_and_caches_it(P):
+    F = torch.from_numpy(P.F).to(DEV)
+    t = eik.tune(F, P.h, P.sources)
+    assert t["candidates"], "first call for this size class times candidates"
+    assert (t["tile"], t["inner_iters"]) in {(c["tile"], c["inner_iters"]) for c in t["candidates"]}
+    assert min(c["ms"] for c in t["candidates"]) == pytest.approx(
+        [c["ms"] for c in t["candidates"] if (c["tile"], c["inner_iters"]) == (t["tile"], t["inner_iters"])][0])
+    again = eik.tune(F, P.h, P.sources)
+    assert again["candidates"] == [] and again["tile"] == t["tile"] and again["inner_iters"] == t["inner_iters"]
+    phi = eik.solve(F, P.h, P.sources, tile=t["tile"], inner_iters=t["inner_iters"]).cpu().numpy()
+    ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+    assert np.max(np.abs(phi - ref)) <= 1e-5 * ref.max()

@@ -19,4 +19,6 @@ from .gen import (  # noqa: F401
     random_problem,
     receivers_on_face,
     flat_index,
+    paper_example,
+    PAPER_SIZES,
 )

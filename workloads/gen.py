@@ -217,3 +217,63 @@ def random_problem(seed: int, ndim: int, max_side: int, dtype=np.float64,
     src = np.sort(r.choice(n, size=k, replace=False)).astype(np.int64)
     hh = float(h) if h is not None else float(r.uniform(0.1, 2.0))
     return Problem(f"random_{ndim}d_{seed}", F.astype(dtype), hh, src, eps=0.0)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own examples (Results section), on n x n nodes over [-10, 10]^2
+# ---------------------------------------------------------------------------
+PAPER_SIZES = (200, 500, 1000, 2000, 4000)
+
+
+def _paper_grid(n: int):
+    """Node coordinates x_j = -10 + j h, h = 20 / (n - 1); axis 0 is y, axis 1 x."""
+    h = 20.0 / (n - 1)
+    c = -10.0 + h * np.arange(n)
+    return h, c[:, None], c[None, :]
+
+
+def _circle_band(F, h, ys, xs, circles):
+    """Nodes within one spacing of a circle become fixed sources valued
+    |dist - R| / F (first-order arrival time from the circle); a node near
+    several circles keeps the smallest value."""
+    best = np.full(F.shape, np.inf)
+    for (cx, cy, R) in circles:
+        d = np.abs(np.sqrt((xs - cx) ** 2 + (ys - cy) ** 2) - R)
+        best = np.where(d <= h, np.minimum(best, d), best)
+    idx = np.flatnonzero(np.isfinite(best))
+    Fv = F.ravel()[idx].astype(np.float64)
+    with np.errstate(divide="ignore"):
+        vals = np.where(Fv > 0, best.ravel()[idx] / np.where(Fv > 0, Fv, 1.0), 0.0)
+    return idx.astype(np.int64), vals
+
+
+def paper_example(k: int, n: int, dtype=np.float32) -> Problem:
+    """Examples 1, 2, 3 and 5 of the paper on an n x n grid over [-10, 10]^2.
+
+    1: F = 1, circle R = 3 at the origin.
+    2: F = 1, circles R = 3 at (2, -5) and R = 1.5 at (-2, 5).
+    3: F = 1 on [3, 7]^2 and 0.01 elsewhere (Eq 7), circles R = 0.5 at (-5, 5)
+       and (5, -5).
+    5: F = sin^2 x + sin^2 y + 0.3 (Eq 9), circle R = 0.5 at the origin.
+    The circles enter as fixed sources on the nodes within one spacing of
+    them (the paper does not state its discretisation of the circles)."""
+    h, ys, xs = _paper_grid(n)
+    if k == 1:
+        F = np.ones((n, n))
+        circles = [(0.0, 0.0, 3.0)]
+    elif k == 2:
+        F = np.ones((n, n))
+        circles = [(2.0, -5.0, 3.0), (-2.0, 5.0, 1.5)]
+    elif k == 3:
+        inside = (xs >= 3) & (xs <= 7) & (ys >= 3) & (ys <= 7)
+        F = np.where(inside, 1.0, 0.01) * np.ones((n, n))
+        circles = [(-5.0, 5.0, 0.5), (5.0, -5.0, 0.5)]
+    elif k == 5:
+        F = np.sin(xs) ** 2 + np.sin(ys) ** 2 + 0.3
+        circles = [(0.0, 0.0, 0.5)]
+    else:
+        raise ValueError("examples 1, 2, 3 and 5 are available (example 4's map is not)")
+    F = F.astype(dtype)
+    src, vals = _circle_band(F, h, ys, xs, circles)
+    return Problem(f"paper_ex{k}_{n}", F, h, src, source_values=vals,
+                   meta={"example": k, "circles": circles})
