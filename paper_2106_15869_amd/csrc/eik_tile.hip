@@ -333,6 +333,7 @@ template <int NT>
 struct TileLists {
     uint32_t flag[2][NT];
     uint16_t list[2][NT];
+    uint8_t dirty[NT];  // remedy: node value changed during this visit
     int cnt[3];
 };
 
@@ -557,8 +558,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
 // the next iteration when the new value lies below theirs (otherwise their
 // update cannot change: the node is not upwind of them), and a face neighbour
 // below the halo value marks that face dirty in the tile across it.
+// Occupancy matters more than a few spilled registers here: the inner
+// iterations are latency-bound, and more resident workgroups hide it (float
+// tiles of up to 512 nodes: eight waves per SIMD measured fastest).
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
+__global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::NPT <= 2) ? 8 : 1) void k_tile_remedy(
+    TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
@@ -593,20 +598,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom
             a.mask_cur[t] = 0u;
         }
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
-        bool ok[S::NPT];
-        int G[S::NPT], L[S::NPT], E[S::NPT];
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             const int nn = threadIdx.x + r * kBlock;
-            int x, y, z;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
-            E[r] = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
-            ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-            G[r] = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
             if (nn < S::NT) {
-                sH[nn] = ok[r] ? cell_H(g.h, a.F[G[r]]) : inf;
+                int x, y, z, L;
+                node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+                const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+                const int G = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+                sH[nn] = ok ? cell_H(g.h, a.F[G]) : inf;
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
+                tl.dirty[nn] = 0;
             }
         }
         if (threadIdx.x == 0) {
@@ -618,15 +621,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom
         }
         __syncthreads();
         // initial remedy list: every non-source node on a first visit, else the
-        // nodes on the faces whose neighbour tile changed
+        // nodes on the faces whose neighbour tile changed (barrier cells and
+        // nodes outside the grid have H = +inf and never change)
         const uint32_t m = s_mask;
-        T phi0[S::NPT];
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            phi0[r] = ok[r] ? sphi[L[r]] : inf;
-            const bool live = ok[r] && (sl[L[r]] & 3u) != L_FIXED;
-            if (live && ((m & kAllFaces) || (E[r] & static_cast<int>(m))))
-                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(threadIdx.x + r * kBlock);
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn >= S::NT) continue;
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
+            const bool live = sH[nn] < inf && (sl[L] & 3u) != L_FIXED;
+            if (live && ((m & kAllFaces) || (E & static_cast<int>(m))))
+                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
         }
         __syncthreads();
         bool pending = false;
@@ -651,6 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom
                 const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
                 if (pt < sphi[Lq] - eps) {
                     sphi[Lq] = pt;
+                    tl.dirty[q] = 1;
                     const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
                     for (int d = 0; d < 2 * ND; ++d) {
@@ -668,20 +676,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom
             __syncthreads();
         }
         if (fm) atomicOr(&s_face, fm);
-        int my_written = 0;
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            if (!ok[r]) continue;
-            const T v = sphi[L[r]];
-            if (v != phi0[r]) {
-                a.phi[G[r]] = v;
-                ++my_written;
-            }
-        }
         if (my_evals) atomicAdd(&s_evals, my_evals);
-        if (my_written) atomicAdd(&s_written, my_written);
         __syncthreads();
-        // scheduling, one lane per target tile (see the update kernel)
+        // scheduling, one lane per target tile (see the update kernel); the
+        // targets are read by the next launch, so these atomics may overlap
+        // the write-back below
         if (threadIdx.x < 7) {
             const int d = threadIdx.x;
             const int fmask = s_face;
@@ -696,12 +695,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_remedy(TileIter<T> a, BatchGeom
                 push_tile(a.next, a.tstamp, tn, ntag);
             }
         }
+        int my_written = 0;
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn >= S::NT || !tl.dirty[nn]) continue;
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            a.phi[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = sphi[L];
+            ++my_written;
+        }
+        if (my_written) atomicAdd(&s_written, my_written);
+        __syncthreads();
         if (threadIdx.x == 0) {
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
             written += static_cast<unsigned long long>(s_written);
         }
-        __syncthreads();
     }
     if (threadIdx.x == 0 && visits) {
         stat_add(a.blkstat, SF_EVALS3, evals);
