@@ -81,7 +81,14 @@ enum {
     EIK_FLAG_ASYNC = 4u,
     /* Bracket every kernel launch with HIP events on the solve's stream and
        report per-kind device time in eik_stats (adds host overhead). */
-    EIK_FLAG_PROFILE = 8u
+    EIK_FLAG_PROFILE = 8u,
+    /* Tile variant: run the remedy loop first-in first-out, every queued tile
+       in every launch.  By default each remedy launch instead processes the
+       queued tiles whose pending values are lowest (about a thousand, chosen
+       by a histogram of per-tile keys) and defers the others, so corrections
+       flow roughly in increasing value and fewer nodes are corrected twice.
+       Same rules and fixed point either way. */
+    EIK_FLAG_FIFO_REMEDY = 16u
 };
 
 /* Kernel kinds of eik_stats.kernel_ms / kernel_launches. */

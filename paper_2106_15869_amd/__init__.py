@@ -46,6 +46,7 @@ EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
 EIK_FLAG_PROFILE = 8
+EIK_FLAG_FIFO_REMEDY = 16
 
 VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
             "tile": EIK_VARIANT_TILE, "fim": EIK_VARIANT_FIM}
@@ -176,7 +177,8 @@ def _check(rc: int):
 
 def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[Sequence[int]] = None,
                  inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
-                 skip_remedy: bool = False, async_: bool = False, profile: bool = False) -> EikOptions:
+                 skip_remedy: bool = False, async_: bool = False, profile: bool = False,
+                 fifo: bool = False) -> EikOptions:
     o = EikOptions()
     _load().eik_default_options(ctypes.byref(o))
     if dtype is not None:
@@ -192,7 +194,8 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
     o.flags = ((EIK_FLAG_DETERMINISTIC if deterministic else 0) |
                (EIK_FLAG_SKIP_REMEDY if skip_remedy else 0) |
                (EIK_FLAG_ASYNC if async_ else 0) |
-               (EIK_FLAG_PROFILE if profile else 0))
+               (EIK_FLAG_PROFILE if profile else 0) |
+               (EIK_FLAG_FIFO_REMEDY if fifo else 0))
     return o
 
 
@@ -255,11 +258,12 @@ def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = 
           source_values=None, deterministic: bool = False, skip_remedy: bool = False,
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
           out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False,
-          async_: bool = False):
+          async_: bool = False, fifo: bool = False):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
-    (and a stats dict when stats=True).  async_=True only enqueues (no host
+    (and a stats dict when stats=True).  fifo=True runs the tile variant's
+    remedy first-in first-out instead of in increasing pending value.  async_=True only enqueues (no host
     synchronisation, capturable in a graph): it needs `workspace`, `out` and
     an explicit `max_iters`, and runs exactly max_iters launches per loop."""
     torch = _torch()
@@ -267,7 +271,7 @@ def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = 
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, async_=async_, profile=profile)
+                       skip_remedy, async_=async_, profile=profile, fifo=fifo)
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     dims = _dims(F.shape)
@@ -410,7 +414,8 @@ def eik_batch_workspace_size(shapes, h, sources, opt: Optional[EikOptions] = Non
 
 def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
                 tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0, out=None,
-                workspace=None, stats: bool = False, stream=None, profile: bool = False, async_: bool = False):
+                workspace=None, stats: bool = False, stream=None, profile: bool = False, async_: bool = False,
+                fifo: bool = False):
     """Solve several independent grids in one call (tile schedule).
 
     F: flat device tensor with the grids back to back (see pack()); shapes:
@@ -422,7 +427,8 @@ def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
     nd, arr, src, shapes = _instances(shapes, h, sources)
     if F.numel() != sum(batch_sizes(shapes)):
         raise ValueError("F must hold exactly the grids of the batch")
-    opt = make_options(_dtype_code(F), "tile", tile, inner_iters, max_iters, async_=async_, profile=profile)
+    opt = make_options(_dtype_code(F), "tile", tile, inner_iters, max_iters, async_=async_, profile=profile,
+                       fifo=fifo)
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     vals = None

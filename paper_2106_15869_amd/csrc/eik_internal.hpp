@@ -122,6 +122,7 @@ template <typename T>
 hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
 hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s);
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_words(void* p, size_t n, uint32_t v, hipStream_t s);  // n 32-bit words
 template <typename T>
 hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
                               hipStream_t s);

@@ -126,6 +126,10 @@ __global__ void k_zero_words(uint32_t* p, int n) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0u;
 }
 
+__global__ void k_fill_words(uint32_t* p, int n, uint32_t v) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // STEP 2
 // ---------------------------------------------------------------------------
@@ -617,6 +621,13 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s) {
     const int n = static_cast<int>(bytes / 4);
     hipLaunchKernelGGL(k_zero_words, dim3(std::min((n + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
                        static_cast<uint32_t*>(p), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_words(void* p, size_t n, uint32_t v, hipStream_t s) {
+    const int m = static_cast<int>(n);
+    hipLaunchKernelGGL(k_fill_words, dim3(std::min((m + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0, s,
+                       static_cast<uint32_t*>(p), m, v);
     return hipGetLastError();
 }
 

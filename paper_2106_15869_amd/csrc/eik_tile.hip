@@ -48,6 +48,14 @@ constexpr int kSub = 8;       // sub-lists per tile list
 constexpr int kPad = 32;      // ints between counters (separate cache lines)
 // Dirty-face mask bit meaning "recheck every node of the tile".
 constexpr uint32_t kAllFaces = 64u;
+// Ordered remedy: per-tile order keys (monotone 32-bit images of the
+// smallest value that made the tile pending), a histogram of them over kBins
+// bins (the top key bits: sign, exponent and the leading mantissa bits), and
+// the number of lowest-key tiles a launch processes at least.
+constexpr int kBins = 8192;
+constexpr int kBinShift = 32 - 13;  // kBins = 2^13
+constexpr int kOrderMin = 1024;
+constexpr uint32_t kNoKey = 0xffffffffu;
 
 
 // A tile list: kSub sub-lists of `cap` tile ids.  count[k * kPad] is the
@@ -73,6 +81,17 @@ struct TileIter {
     // staged the neighbour's values before the change that set it.
     uint32_t* mask_cur;
     uint32_t* mask_next;
+    // ordered remedy (the default; EIK_FLAG_FIFO_REMEDY turns it off): keys by
+    // launch parity, histograms rotating like the list counters
+    uint32_t* key_cur;
+    uint32_t* key_next;
+    unsigned* hist_cur;
+    unsigned* hist_next;
+    unsigned* hist_zero;
+    int ordered;
+    TList work;              // ordered: the tiles of this launch, split off by k_tile_split
+    int* work_zero_count;    // counters of the other work list: cleared by the remedy launch
+    int* work_zero_fetch;
     TList cur;
     TList next;
     int* zero_count;   // counters of the list two launches ahead: cleared by this launch
@@ -244,11 +263,62 @@ __device__ __forceinline__ void launch_stats(const TileIter<T>& a, int n) {
 }
 
 // Claim tile t for the next list and append it to sub-list t % kSub.
-__device__ __forceinline__ void push_tile(const TList& out, uint32_t* tstamp, int t, uint32_t tag) {
-    if (!claim_tile(tstamp, t, tag)) return;
+__device__ __forceinline__ bool push_tile(const TList& out, uint32_t* tstamp, int t, uint32_t tag) {
+    if (!claim_tile(tstamp, t, tag)) return false;
     const int k = t & (kSub - 1);
     const int pos = atomicAdd(out.count + k * kPad, 1);
     out.data[static_cast<size_t>(k) * out.cap + pos] = t;
+    return true;
+}
+
+// Order key of a value: unsigned integers compare like the (float) values.
+template <typename T>
+__device__ __forceinline__ uint32_t order_key(T v) {
+    const uint32_t b = __float_as_uint(static_cast<float>(v));
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ int key_bin(uint32_t key) { return static_cast<int>(key >> kBinShift); }
+
+// push_tile for the remedy: in ordered mode also lower the tile's key and
+// count the claim in the next list's histogram.
+template <typename T>
+__device__ __forceinline__ void push_keyed(const TileIter<T>& a, int t, uint32_t tag, uint32_t key) {
+    if (a.ordered) atomicMin(a.key_next + t, key);
+    if (push_tile(a.next, a.tstamp, t, tag) && a.ordered) atomicAdd(a.hist_next + key_bin(key), 1u);
+}
+
+// Ordered remedy: the largest histogram bin whose tiles this launch
+// processes -- the first bin where the running count reaches
+// min(list length, kOrderMin).  Block-wide; block 0 also clears the
+// histogram of the list two launches ahead.
+template <typename T>
+__device__ __forceinline__ int order_threshold(const TileIter<T>& a, int n, int* s_thr) {
+    constexpr int PER = kBins / kBlock;
+    __shared__ int s_wave[kBlock / 64];
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_zero[j] = 0u;
+    const unsigned* h = a.hist_cur + threadIdx.x * PER;
+    int sum = 0;
+    for (int j = 0; j < PER; ++j) sum += static_cast<int>(h[j]);
+    const int incl = wave_incl_scan(sum);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) s_wave[w] = incl;
+    if (threadIdx.x == 0) *s_thr = kBins - 1;
+    __syncthreads();
+    int run = incl - sum;
+    for (int q = 0; q < w; ++q) run += s_wave[q];
+    const int need = min(n, kOrderMin);
+    if (run < need && run + sum >= need) {  // exactly one thread holds the crossing bin
+        for (int j = 0; j < PER; ++j) {
+            run += static_cast<int>(h[j]);
+            if (run >= need) {
+                *s_thr = threadIdx.x * PER + j;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    return *s_thr;
 }
 
 // Clear the counters of the list two launches ahead (nobody reads or writes
@@ -526,27 +596,36 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
+    __shared__ uint32_t s_key;
     const uint32_t ntag = launch_tag(a);
     for (int t = blockIdx.x; t < bg.ntiles; t += gridDim.x) {
         const Inst<T> g = inst_of(bg, t);
         const int lt = t - g.tile_base;
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        if (threadIdx.x == 0) s_key = kNoKey;  // ordered below the staging barrier
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         Owned<T, S::NPT> o;
         own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, o);
         __syncthreads();
         bool flag = false;
+        T low = pos_inf<T>();
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
             const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
-            flag |= pt < sphi[o.L[r]] - eps;
+            if (pt < sphi[o.L[r]] - eps) {
+                flag = true;
+                low = tmin(low, pt);
+            }
         }
+        if (a.ordered && flag) atomicMin(&s_key, order_key(low));
         if (__syncthreads_or(flag) && threadIdx.x == 0) {
             a.mask_next[t] = kAllFaces;  // one writer: the workgroup of tile t
-            push_tile(a.next, a.tstamp, t, ntag);
+            if (a.ordered) a.key_next[t] = s_key;
+            push_keyed(a, t, ntag, s_key);
         }
+        __syncthreads();
     }
 }
 
@@ -575,15 +654,39 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
     __shared__ int s_evals;
     __shared__ int s_written;
     __shared__ uint32_t s_mask;
+    __shared__ uint32_t s_key, s_kmin;
     const T inf = pos_inf<T>();
     const uint32_t ntag = launch_tag(a);
     const int n = list_open(a, s_len);
     launch_stats(a, n);
+    // ordered mode: k_tile_split has moved this launch's tiles into the work
+    // list (the rest went on to the next list)
+    const TList src = a.ordered ? a.work : a.cur;
+    if (a.ordered) {
+        __syncthreads();  // s_len of the current list has been read
+        if (threadIdx.x < kSub) s_len[threadIdx.x] = a.work.count[threadIdx.x * kPad];
+        if (blockIdx.x == 0 && threadIdx.x < kSub) {
+            a.work_zero_count[threadIdx.x * kPad] = 0;
+            a.work_zero_fetch[threadIdx.x * kPad] = 0;
+        }
+        __syncthreads();
+    }
     const int k = blockIdx.x & (kSub - 1);
     const int len = s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
     for (;;) {
-        const int t = list_fetch(a.cur, k, len, &s_slot);
+        if (threadIdx.x == 0) {
+            const int e = atomicAdd(src.fetch + k * kPad, 1);
+            const int tt = e < len ? src.data[static_cast<size_t>(k) * src.cap + e] : -1;
+            if (tt >= 0 && a.ordered) {
+                s_key = a.key_cur[tt];
+                a.key_cur[tt] = kNoKey;
+            }
+            s_slot = tt;
+        }
+        __syncthreads();
+        const int t = s_slot;
+        __syncthreads();
         if (t < 0) break;
         ++visits;
         const Inst<T> g = inst_of(bg, t);
@@ -596,6 +699,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
             // written by the previous launch; no writer during this one
             mask_in = a.mask_cur[t];
             a.mask_cur[t] = 0u;
+            s_kmin = kNoKey;
         }
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
 #pragma unroll
@@ -638,6 +742,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
         __syncthreads();
         bool pending = false;
         int my_evals = 0, fm = 0;
+        T kmin = inf;  // smallest value that crossed a face (order key of the pushes)
         int it = 0;
         for (;; ++it) {
             const int ncur = tl.cnt[it % 3];
@@ -665,7 +770,10 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
                         const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
                         if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
                         if (edge & (1 << d)) {
-                            if (open & (1 << d)) fm |= 1 << d;
+                            if (open & (1 << d)) {
+                                fm |= 1 << d;
+                                kmin = tmin(kmin, pt);
+                            }
                         } else {
                             const uint8_t lb = sl[Ln];
                             if (!(lb & kOut) && (lb & 3u) != L_FIXED) list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
@@ -677,6 +785,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
         }
         if (fm) atomicOr(&s_face, fm);
         if (my_evals) atomicAdd(&s_evals, my_evals);
+        if (a.ordered && kmin < inf) atomicMin(&s_kmin, order_key(kmin));
         __syncthreads();
         // scheduling, one lane per target tile (see the update kernel); the
         // targets are read by the next launch, so these atomics may overlap
@@ -684,15 +793,16 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
         if (threadIdx.x < 7) {
             const int d = threadIdx.x;
             const int fmask = s_face;
+            const uint32_t key = s_kmin;
             if (d == 6) {
                 if (pending) {
                     atomicOr(a.mask_next + t, kAllFaces);
-                    push_tile(a.next, a.tstamp, t, ntag);
+                    push_keyed(a, t, ntag, min(key, s_key));
                 }
             } else if (d < 2 * ND && (fmask & (1 << d))) {
                 const int tn = neighbour_tile(g, t, d);
                 atomicOr(a.mask_next + tn, 1u << (d ^ 1));  // the face of tn shared with t
-                push_tile(a.next, a.tstamp, tn, ntag);
+                push_keyed(a, tn, ntag, key);
             }
         }
         int my_written = 0;
@@ -718,6 +828,40 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
         stat_add(a.blkstat, SF_VISITS3, visits);
         stat_add(a.blkstat, SF_INNER3, inner_sum);
         stat_add(a.blkstat, SF_WRITTEN3, written);
+    }
+}
+
+// Ordered remedy: before each remedy launch, one lane per entry of the
+// current list sends the tile either to the work list of the launch (its key
+// is within the threshold of order_threshold) or on to the next list with its
+// key and dirty faces.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile_split(TileIter<T> a) {
+    __shared__ int s_len[kSub];
+    __shared__ int s_thr;
+    const uint32_t ntag = launch_tag(a);
+    if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
+    __syncthreads();
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) n += s_len[k];
+    if (n == 0) return;
+    const int thr = order_threshold(a, n, &s_thr);
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
+        int k = 0, i = e;
+        while (i >= s_len[k]) i -= s_len[k++];
+        const int t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
+        const uint32_t key = a.key_cur[t];
+        if (key_bin(key) <= thr) {
+            const int w = t & (kSub - 1);
+            a.work.data[static_cast<size_t>(w) * a.work.cap + atomicAdd(a.work.count + w * kPad, 1)] = t;
+        } else {
+            a.key_cur[t] = kNoKey;
+            const uint32_t mk = a.mask_cur[t];
+            a.mask_cur[t] = 0u;
+            if (mk) atomicOr(a.mask_next + t, mk);
+            push_keyed(a, t, ntag, key);
+        }
     }
 }
 
@@ -764,16 +908,24 @@ struct TileWs {
     uint32_t* tstamp;
     uint32_t* tmask;    // two arrays of ntiles dirty-face masks (by launch parity)
     int* data[2];       // two list buffers (alternating)
-    int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}
+    int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}, then
+                        // 3 rotating order-key histograms of kBins counts
+    uint32_t* keys;     // two arrays of ntiles order keys (by launch parity)
+    int* work[2];       // ordered remedy: work lists (by launch parity) ...
+    int* work_counters; // ... and their {count, fetch} sets
     void* table;        // instance table (batches of more than one instance)
     int* tile_inst;     // instance of every tile (idem)
     int cap;
     size_t bytes;
     int* count_of(int set) const { return counters + set * 2 * kSub * kPad; }
     int* fetch_of(int set) const { return counters + set * 2 * kSub * kPad + kSub * kPad; }
+    unsigned* hist_of(int set) const {
+        return reinterpret_cast<unsigned*>(counters + 3 * 2 * kSub * kPad) + set * kBins;
+    }
 };
 
-constexpr size_t kCounterBytes = 3 * 2 * kSub * kPad * sizeof(int);
+constexpr size_t kCounterBytes = (3 * 2 * kSub * kPad + 3 * kBins) * sizeof(int);
+constexpr size_t kWorkCounterBytes = 2 * 2 * kSub * kPad * sizeof(int);
 
 // A sub-list can receive every tile (tiles are deduplicated per list).
 TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t inst_bytes) {
@@ -791,6 +943,9 @@ TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t i
     w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
     w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
     w.counters = reinterpret_cast<int*>(take(kCounterBytes));
+    w.keys = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
+    for (int k = 0; k < 2; ++k) w.work[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
+    w.work_counters = reinterpret_cast<int*>(take(kWorkCounterBytes));
     for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
     if (ninst > 1) {
         w.table = take(inst_bytes * ninst);
@@ -922,6 +1077,12 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
     launched += 5;
+    const bool ordered = (o.flags & EIK_FLAG_FIFO_REMEDY) == 0;
+    if (ordered) {
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_fill_words(w.keys, 2 * static_cast<size_t>(ntiles), kNoKey, s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.work_counters, kWorkCounterBytes, s); }));
+        launched += 2;
+    }
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> sb{};
@@ -975,6 +1136,23 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         a.tstamp = w.tstamp;
         a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * ntiles;
         a.mask_next = w.tmask + static_cast<size_t>((t + 1) & 1) * ntiles;
+        a.key_cur = w.keys + static_cast<size_t>(t & 1) * ntiles;
+        a.key_next = w.keys + static_cast<size_t>((t + 1) & 1) * ntiles;
+        a.hist_cur = w.hist_of(static_cast<int>(t % 3));
+        a.hist_next = w.hist_of(static_cast<int>((t + 1) % 3));
+        a.hist_zero = w.hist_of(static_cast<int>((t + 2) % 3));
+        a.ordered = (ordered && phase == 1) ? 1 : 0;
+        auto work_of = [&](int64_t u) {
+            TList L;
+            L.data = w.work[u & 1];
+            L.count = w.work_counters + (u & 1) * 2 * kSub * kPad;
+            L.fetch = L.count + kSub * kPad;
+            L.cap = w.cap;
+            return L;
+        };
+        a.work = work_of(t);
+        a.work_zero_count = work_of(t + 1).count;
+        a.work_zero_fetch = work_of(t + 1).fetch;
         a.cur = list_of(t);
         a.next = list_of(t + 1);
         a.zero_count = w.count_of(static_cast<int>((t + 2) % 3));
@@ -1002,18 +1180,29 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         TileIter<T> d = iter_args(0, 1);  // only `next` (list 0), its masks and the tag are used
         d.next = list_of(0);
         d.mask_next = w.tmask;  // read by remedy launch 0
+        d.key_next = w.keys;
+        d.hist_next = w.hist_of(0);
         d.first = 0;
         d.tag_slot = static_cast<int>(gl & 1);
         HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, geom, eT, s); }));
         gl += 1;
         launched += 2;
         int64_t n3 = 0;
+        const int split_blocks = static_cast<int>(std::min<int64_t>((b.ntiles + kBlock - 1) / kBlock, 1024));
         rc = run_loop(
             [&](int64_t t) {
-                return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(iter_args(t, 1), geom, eT, inner, s); });
+                const TileIter<T> a = iter_args(t, 1);
+                if (ordered) {
+                    const hipError_t e = timed(prof, EIK_KERNEL_OTHER, [&] {
+                        hipLaunchKernelGGL(k_tile_split<T>, dim3(split_blocks), dim3(kBlock), 0, s, a);
+                        return hipGetLastError();
+                    });
+                    if (e != hipSuccess) return e;
+                }
+                return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(a, geom, eT, inner, s); });
             },
             counts, kSub * kPad, cap, async, s, &n3);
-        launched += n3;
+        launched += (ordered ? 2 : 1) * n3;
     }
     if (async) return rc;
     HostSlots& hs = host_slots();

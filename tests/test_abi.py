@@ -150,6 +150,8 @@ def test_invalid_options_rejected(lib):
     assert "remedy" in lib.eik_last_error().decode()
     o = eik.make_options(eik.EIK_FLOAT32, "fim", deterministic=True)
     assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+    o = eik.make_options(eik.EIK_FLOAT32, "node", fifo=True)
+    assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT  # a tile-schedule choice
     o = eik.make_options(eik.EIK_FLOAT32, "node")
     o.variant = 3
     assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT

@@ -18,10 +18,14 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
+SCHEDULE = {"node": dict(variant="node"), "tile": dict(variant="tile"), "fim": dict(variant="fim"),
+            "fifo": dict(variant="tile", fifo=True)}
+
+
 def _check(P, variant):
     print(f"[case] fullsize {P.name} {variant}", flush=True)
     F = torch.from_numpy(P.F).to(DEV)
-    phi, st = eik.solve(F, P.h, P.sources, variant=variant, stats=True)
+    phi, st = eik.solve(F, P.h, P.sources, stats=True, **SCHEDULE[variant])
     got = phi.cpu().numpy().astype(np.float64)
     print(f"[stats] {st}", flush=True)
     ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
@@ -35,7 +39,7 @@ def _check(P, variant):
     return got, ref
 
 
-@pytest.mark.parametrize("variant", ["tile", "node"])
+@pytest.mark.parametrize("variant", ["tile", "node", "fim", "fifo"])
 def test_maze_256(variant):
     P = W.maze_3d(256)
     got, _ = _check(P, variant)
@@ -43,7 +47,7 @@ def test_maze_256(variant):
     assert H.equation_residual(P.F, P.h, got, P.sources) < 1e-5
 
 
-@pytest.mark.parametrize("variant", ["tile", "node"])
+@pytest.mark.parametrize("variant", ["tile", "node", "fifo"])
 def test_lognormal_4096(variant):
     P = W.lognormal_2d(4096)
     _check(P, variant)

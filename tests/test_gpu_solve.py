@@ -19,7 +19,9 @@ eik = pytest.importorskip("paper_2106_15869_amd")
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = {np.float32: 1e-5, np.float64: 1e-12}
-VARIANTS = ["node", "tile", "fim"]
+VARIANTS = ["node", "tile", "fim", "fifo"]
+SCHEDULE = {"node": dict(variant="node"), "tile": dict(variant="tile"), "fim": dict(variant="fim"),
+            "fifo": dict(variant="tile", fifo=True)}
 
 
 def dev(a):
@@ -128,7 +130,7 @@ def test_update_step_alone_exact_for_single_constant_front():
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("P", fuzz_cases() + workload_cases(), ids=lambda P: P.name)
 def test_solve_matches_oracle(P, dtype, variant):
-    got, st = gpu_solve(P, dtype, variant=variant)
+    got, st = gpu_solve(P, dtype, **SCHEDULE[variant])
     assert_close(got, ref_solve(P, dtype), dtype)
 
 
@@ -161,7 +163,7 @@ def _edge_cases():
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("P", _edge_cases(), ids=lambda P: P.name)
 def test_edge_cases(P, dtype, variant):
-    got, _ = gpu_solve(P, dtype, variant=variant)
+    got, _ = gpu_solve(P, dtype, **SCHEDULE[variant])
     assert_close(got, ref_solve(P, dtype), dtype)
 
 
@@ -170,18 +172,18 @@ def test_invalid_speed_reported(variant):
     F = np.ones((16, 16), dtype=np.float32)
     F[3, 4] = -1.0
     with pytest.raises(eik.EikError) as e:
-        eik.solve(dev(F), 1.0, [0], variant=variant)
+        eik.solve(dev(F), 1.0, [0], **SCHEDULE[variant])
     assert e.value.status == eik.EIK_ERR_INVALID_ARGUMENT
     F[3, 4] = np.nan
     with pytest.raises(eik.EikError):
-        eik.solve(dev(F), 1.0, [0], variant=variant)
+        eik.solve(dev(F), 1.0, [0], **SCHEDULE[variant])
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_iteration_cap_reported(variant):
     P = W.lognormal_2d(64)
     with pytest.raises(eik.EikError) as e:
-        eik.solve(dev(P.F), P.h, P.sources, variant=variant, max_iters=2)
+        eik.solve(dev(P.F), P.h, P.sources, max_iters=2, **SCHEDULE[variant])
     assert e.value.status == eik.EIK_ERR_NO_CONVERGENCE
 
 
