@@ -75,6 +75,23 @@ def _load():
         lib.eo_ifim_f.argtypes = [i, P, d, P, P, P, i64, d, i, i64, P, P]
         lib.eo_fim.restype = i
         lib.eo_fim.argtypes = [i, P, d, P, P, P, i64, d, i64, P, P]
+        # per-axis spacing variants (extra spacing pointer after h)
+        lib.eo_godunov_aniso.restype = d
+        lib.eo_godunov_aniso.argtypes = [i, P, P]
+        lib.eo_godunov_aniso_f.restype = f
+        lib.eo_godunov_aniso_f.argtypes = [i, P, P]
+        lib.eo_apply_local_a.restype = i
+        lib.eo_apply_local_a.argtypes = [i, P, d, P, P, P, P]
+        lib.eo_apply_local_af.restype = i
+        lib.eo_apply_local_af.argtypes = [i, P, P, P, P, P]
+        lib.eo_fmm_a.restype = i
+        lib.eo_fmm_a.argtypes = [i, P, d, P, P, P, P, i64, P, P, P]
+        lib.eo_fsm_a.restype = i
+        lib.eo_fsm_a.argtypes = [i, P, d, P, P, P, P, i64, P, i, i64, P]
+        lib.eo_fim_a.restype = i
+        lib.eo_fim_a.argtypes = [i, P, d, P, P, P, P, i64, d, i64, P, P]
+        lib.eo_adjoint_a.restype = i
+        lib.eo_adjoint_a.argtypes = [i, P, d, P, P, P, i64, P, P, P, P]
         if hasattr(lib, "eo_adjoint"):
             lib.eo_adjoint.restype = i
             lib.eo_adjoint.argtypes = [i, P, d, P, P, i64, P, P, P, P]
@@ -112,8 +129,48 @@ def godunov_bisect(a: Sequence[float], H: float) -> float:
     return float(_load().eo_godunov_bisect(len(arr), _ptr(arr), float(H)))
 
 
-def apply_local(F, h: float, phi, dtype=np.float64) -> np.ndarray:
-    """G_i(phi) at every node, in float64 (default) or float32 arithmetic."""
+def _spacing(spacing, ndim):
+    if spacing is None:
+        return None
+    sp = np.ascontiguousarray(np.asarray(spacing, dtype=np.float64).ravel())
+    if sp.size != ndim or not np.all(np.isfinite(sp)) or not np.all(sp > 0):
+        raise ValueError("spacing needs one finite positive entry per axis")
+    return sp
+
+
+def godunov_aniso(a: Sequence[float], H: Sequence[float], dtype=np.float64) -> float:
+    """Local solve with a per-axis H_k = spacing_k / F (Eq 5 with dx != dy)."""
+    if np.dtype(dtype) == np.float32:
+        aa = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        hh = np.ascontiguousarray(np.asarray(H, dtype=np.float32))
+        return np.float32(_load().eo_godunov_aniso_f(len(aa), _ptr(aa), _ptr(hh)))
+    aa = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    hh = np.ascontiguousarray(np.asarray(H, dtype=np.float64))
+    return float(_load().eo_godunov_aniso(len(aa), _ptr(aa), _ptr(hh)))
+
+
+def apply_local(F, h: float, phi, dtype=np.float64, spacing=None) -> np.ndarray:
+    """G_i(phi) at every node, in float64 (default) or float32 arithmetic;
+    spacing (one per axis, dims order) replaces the isotropic h."""
+    sp = _spacing(spacing, np.ndim(F))
+    if sp is not None:
+        if np.dtype(dtype) == np.float32:
+            F32 = np.ascontiguousarray(np.asarray(F), dtype=np.float32)
+            p32 = np.ascontiguousarray(np.asarray(phi), dtype=np.float32)
+            o32 = np.empty_like(F32)
+            dims = np.asarray(F32.shape, dtype=np.int64)
+            rc = _load().eo_apply_local_af(F32.ndim, _ptr(dims), _ptr(sp), _ptr(F32), _ptr(p32), _ptr(o32))
+            if rc:
+                raise ValueError("eo_apply_local_af failed: %d" % rc)
+            return o32
+        F64 = np.ascontiguousarray(np.asarray(F), dtype=np.float64)
+        p = np.ascontiguousarray(np.asarray(phi), dtype=np.float64)
+        out = np.empty_like(F64)
+        dims = np.asarray(F64.shape, dtype=np.int64)
+        rc = _load().eo_apply_local_a(F64.ndim, _ptr(dims), float(h), _ptr(sp), _ptr(F64), _ptr(p), _ptr(out))
+        if rc:
+            raise ValueError("eo_apply_local_a failed: %d" % rc)
+        return out
     if np.dtype(dtype) == np.float32:
         F32 = np.ascontiguousarray(np.asarray(F), dtype=np.float32)
         p32 = np.ascontiguousarray(np.asarray(phi), dtype=np.float32)
@@ -133,15 +190,17 @@ def apply_local(F, h: float, phi, dtype=np.float64) -> np.ndarray:
     return out
 
 
-def fmm(F, h: float, sources, values=None, return_order: bool = False):
-    """Fast-marching solution (float64) of the discrete system."""
+def fmm(F, h: float, sources, values=None, return_order: bool = False, spacing=None):
+    """Fast-marching solution (float64) of the discrete system; spacing (one
+    per axis, dims order) replaces the isotropic h."""
     F64, dims, src, val = _prep(F, sources, values)
+    sp = _spacing(spacing, F64.ndim)
     phi = np.empty_like(F64)
     order = np.empty(F64.size, dtype=np.int64) if return_order else None
     nacc = ctypes.c_int64(0)
-    rc = _load().eo_fmm(F64.ndim, _ptr(dims), float(h), _ptr(F64), _ptr(src),
-                        None if val is None else _ptr(val), len(src), _ptr(phi),
-                        None if order is None else _ptr(order), ctypes.byref(nacc))
+    rc = _load().eo_fmm_a(F64.ndim, _ptr(dims), float(h), None if sp is None else _ptr(sp), _ptr(F64),
+                          _ptr(src), None if val is None else _ptr(val), len(src), _ptr(phi),
+                          None if order is None else _ptr(order), ctypes.byref(nacc))
     if rc:
         raise ValueError("eo_fmm failed: %d" % rc)
     if return_order:
@@ -149,14 +208,15 @@ def fmm(F, h: float, sources, values=None, return_order: bool = False):
     return phi
 
 
-def fsm(F, h: float, sources, values=None, bisect: bool = False, max_passes: int = 100000):
+def fsm(F, h: float, sources, values=None, bisect: bool = False, max_passes: int = 100000, spacing=None):
     """Fast-sweeping (Gauss-Seidel) solution; returns (phi, passes)."""
     F64, dims, src, val = _prep(F, sources, values)
+    sp = _spacing(spacing, F64.ndim)
     phi = np.empty_like(F64)
     passes = ctypes.c_int64(0)
-    rc = _load().eo_fsm(F64.ndim, _ptr(dims), float(h), _ptr(F64), _ptr(src),
-                        None if val is None else _ptr(val), len(src), _ptr(phi),
-                        1 if bisect else 0, int(max_passes), ctypes.byref(passes))
+    rc = _load().eo_fsm_a(F64.ndim, _ptr(dims), float(h), None if sp is None else _ptr(sp), _ptr(F64),
+                          _ptr(src), None if val is None else _ptr(val), len(src), _ptr(phi),
+                          1 if bisect else 0, int(max_passes), ctypes.byref(passes))
     if rc:
         raise ValueError("eo_fsm failed: %d" % rc)
     return phi, int(passes.value)
@@ -186,15 +246,17 @@ def ifim(F, h: float, sources, values=None, eps: float = 0.0, skip_remedy: bool 
 FIM_STAT_NAMES = ("iters", "evals_update", "evals_check", "max_active")
 
 
-def fim(F, h: float, sources, values=None, eps: float = 0.0, max_iters: Optional[int] = None):
+def fim(F, h: float, sources, values=None, eps: float = 0.0, max_iters: Optional[int] = None, spacing=None):
     """The fast iterative method (Section 2.3), serial, synchronous reads per
     iteration, float64; returns (phi, stats dict)."""
     F64, dims, src, val = _prep(F, sources, values)
+    sp = _spacing(spacing, F64.ndim)
     phi = np.empty(F64.shape, dtype=np.float64)
     stats = np.zeros(len(FIM_STAT_NAMES), dtype=np.int64)
     cap = int(max_iters) if max_iters is not None else 4 * F64.size + 16
-    rc = _load().eo_fim(F64.ndim, _ptr(dims), float(h), _ptr(F64), _ptr(src),
-                        None if val is None else _ptr(val), len(src), float(eps), cap, _ptr(phi), _ptr(stats))
+    rc = _load().eo_fim_a(F64.ndim, _ptr(dims), float(h), None if sp is None else _ptr(sp), _ptr(F64),
+                          _ptr(src), None if val is None else _ptr(val), len(src), float(eps), cap, _ptr(phi),
+                          _ptr(stats))
     if rc == EO_NOCONV:
         raise RuntimeError("eo_fim: iteration cap reached")
     if rc:
@@ -202,17 +264,18 @@ def fim(F, h: float, sources, values=None, eps: float = 0.0, max_iters: Optional
     return phi, dict(zip(FIM_STAT_NAMES, (int(v) for v in stats)))
 
 
-def adjoint(F, h: float, sources, phi, dL_dphi, values=None):
+def adjoint(F, h: float, sources, phi, dL_dphi, values=None, spacing=None):
     """dL/dF for a loss L(phi), by reverse sweep in acceptance order (float64)."""
     lib = _load()
     if not hasattr(lib, "eo_adjoint"):
         raise NotImplementedError("oracle adjoint not built")
     F64, dims, src, val = _prep(F, sources, values)
+    sp = _spacing(spacing, F64.ndim)
     p = np.ascontiguousarray(np.asarray(phi), dtype=np.float64)
     g = np.ascontiguousarray(np.asarray(dL_dphi), dtype=np.float64)
     out = np.empty_like(F64)
-    rc = lib.eo_adjoint(F64.ndim, _ptr(dims), float(h), _ptr(F64), _ptr(src), len(src),
-                        _ptr(p), _ptr(g), _ptr(out), None)
+    rc = lib.eo_adjoint_a(F64.ndim, _ptr(dims), float(h), None if sp is None else _ptr(sp), _ptr(F64),
+                          _ptr(src), len(src), _ptr(p), _ptr(g), _ptr(out), None)
     if rc:
         raise ValueError("eo_adjoint failed: %d" % rc)
     return out

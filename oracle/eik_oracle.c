@@ -35,6 +35,9 @@
  *       once -- if its value drops it takes the new value and (re)joins the
  *       active list.  Counters: iterations, active evaluations, neighbour-check
  *       evaluations, peak list length.
+ *   *_a variants (eo_fmm_a, eo_fsm_a, eo_fim_a, eo_apply_local_a,
+ *       eo_adjoint_a) take a per-axis spacing (Eq 5 with dx != dy, Algorithm
+ *       1.2, and its 3D analogue), solved by eo_godunov_aniso.
  *   eo_adjoint : reverse sweep in fast-marching acceptance order giving
  *       dL/dF for a loss L(phi) (the linearised upwind system, transposed).
  *
@@ -150,6 +153,69 @@ float eo_godunov_f(int m, const float* a_in, float H) {
     return phi;
 }
 
+/*
+ * Anisotropic local solve (Eq 5 with dx != dy, the equation Algorithm 1.2
+ * solves, and its 3D analogue): the root of
+ *     sum_k ((phi - a_k)^+ / H_k)^2 = 1,   H_k = (spacing along axis k) / F,
+ * by the same progressive rule on the a_k sorted ascending (each H_k travels
+ * with its a_k), in shifted form: with t = phi - a_1, b_k = a_k - a_1 and
+ * w_k = 1 / H_k^2 the active axes give A t^2 - 2 B t + C = 0,
+ * A = sum w_k, B = sum w_k b_k, C = sum w_k b_k^2 - 1.
+ */
+double eo_godunov_aniso(int m, const double* a_in, const double* H_in) {
+    double a[3], H[3];
+    for (int k = 0; k < m; ++k) { a[k] = a_in[k]; H[k] = H_in[k]; }
+    for (int k = 1; k < m; ++k) {
+        double v = a[k], hv = H[k];
+        int j = k - 1;
+        while (j >= 0 && a[j] > v) { a[j + 1] = a[j]; H[j + 1] = H[j]; --j; }
+        a[j + 1] = v;
+        H[j + 1] = hv;
+    }
+    if (!(a[0] < INFINITY) || !(H[0] < INFINITY)) return INFINITY;
+    double phi = a[0] + H[0];
+    double A = 1.0 / (H[0] * H[0]), B = 0.0, C = -1.0;
+    for (int k = 1; k < m; ++k) {
+        if (!(phi > a[k])) break;
+        double b = a[k] - a[0];
+        double w = 1.0 / (H[k] * H[k]);
+        A += w;
+        B += w * b;
+        C += w * b * b;
+        double disc = B * B - A * C;
+        if (disc < 0.0) disc = 0.0;
+        phi = a[0] + (B + sqrt(disc)) / A;
+    }
+    return phi;
+}
+
+float eo_godunov_aniso_f(int m, const float* a_in, const float* H_in) {
+    float a[3], H[3];
+    for (int k = 0; k < m; ++k) { a[k] = a_in[k]; H[k] = H_in[k]; }
+    for (int k = 1; k < m; ++k) {
+        float v = a[k], hv = H[k];
+        int j = k - 1;
+        while (j >= 0 && a[j] > v) { a[j + 1] = a[j]; H[j + 1] = H[j]; --j; }
+        a[j + 1] = v;
+        H[j + 1] = hv;
+    }
+    if (!(a[0] < INFINITY) || !(H[0] < INFINITY)) return INFINITY;
+    float phi = a[0] + H[0];
+    float A = 1.0f / (H[0] * H[0]), B = 0.0f, C = -1.0f;
+    for (int k = 1; k < m; ++k) {
+        if (!(phi > a[k])) break;
+        float b = a[k] - a[0];
+        float w = 1.0f / (H[k] * H[k]);
+        A += w;
+        B += w * b;
+        C += w * b * b;
+        float disc = B * B - A * C;
+        if (disc < 0.0f) disc = 0.0f;
+        phi = a[0] + (B + sqrtf(disc)) / A;
+    }
+    return phi;
+}
+
 /* residual r(phi) = sum_k ((phi - a_k)^+)^2 - H^2, increasing in phi */
 static double godunov_residual(int m, const double* a, double H, double phi) {
     double r = -H * H;
@@ -198,17 +264,32 @@ static void axis_mins_f(const grid_t* g, const float* phi, int64_t i, float* a) 
 
 static double node_H(double h, double F) { return F > 0.0 ? h / F : INFINITY; }
 
-/* G_i(phi) for every node (sources included), FP64 */
-int eo_apply_local(int ndim, const int64_t* dims, double h, const double* F,
-                   const double* phi, double* out) {
+/* G_i from the axis minima: isotropic spacing h, or per-axis spacing dsp
+ * (axis order of dims) when dsp is not NULL */
+static double local_solve(int nd, const double* a, double F, double h, const double* dsp) {
+    if (!dsp) return eo_godunov(nd, a, node_H(h, F));
+    if (!(F > 0.0)) return INFINITY;
+    double Hk[3];
+    for (int k = 0; k < nd; ++k) Hk[k] = dsp[k] / F;
+    return eo_godunov_aniso(nd, a, Hk);
+}
+
+/* G_i(phi) for every node (sources included), FP64; dsp as local_solve */
+int eo_apply_local_a(int ndim, const int64_t* dims, double h, const double* dsp, const double* F,
+                     const double* phi, double* out) {
     grid_t g;
     if (grid_init(&g, ndim, dims)) return EO_BAD;
     double a[3];
     for (int64_t i = 0; i < g.n; ++i) {
         axis_mins(&g, phi, i, a);
-        out[i] = eo_godunov(g.nd, a, node_H(h, F[i]));
+        out[i] = local_solve(g.nd, a, F[i], h, dsp);
     }
     return EO_OK;
+}
+
+int eo_apply_local(int ndim, const int64_t* dims, double h, const double* F,
+                   const double* phi, double* out) {
+    return eo_apply_local_a(ndim, dims, h, NULL, F, phi, out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -275,7 +356,7 @@ static hnode heap_pop(heap_t* h) {
 
 /* tentative value of i from ACCEPTED neighbours only */
 static double tentative(const grid_t* g, const double* phi, const unsigned char* acc,
-                        int64_t i, double H) {
+                        int64_t i, double F, double h, const double* dsp) {
     double a[3];
     for (int k = 0; k < g->nd; ++k) {
         int64_t x = coord(g, i, k);
@@ -284,7 +365,7 @@ static double tentative(const grid_t* g, const double* phi, const unsigned char*
         if (x + 1 < g->d[k] && acc[i + g->s[k]] && phi[i + g->s[k]] < v) v = phi[i + g->s[k]];
         a[k] = v;
     }
-    return eo_godunov(g->nd, a, H);
+    return local_solve(g->nd, a, F, h, dsp);
 }
 
 /*
@@ -292,9 +373,9 @@ static double tentative(const grid_t* g, const double* phi, const unsigned char*
  * accept_order (nullable, length N) receives the flat indices in acceptance
  * order (sources first, in index order); *n_accepted its length.
  */
-int eo_fmm(int ndim, const int64_t* dims, double h, const double* F,
-           const int64_t* src, const double* val, int64_t nsrc, double* phi,
-           int64_t* accept_order, int64_t* n_accepted) {
+int eo_fmm_a(int ndim, const int64_t* dims, double h, const double* dsp, const double* F,
+             const int64_t* src, const double* val, int64_t nsrc, double* phi,
+             int64_t* accept_order, int64_t* n_accepted) {
     grid_t g;
     if (grid_init(&g, ndim, dims) || nsrc < 1 || !(h > 0.0)) return EO_BAD;
     unsigned char* acc = (unsigned char*)malloc((size_t)g.n);
@@ -314,7 +395,7 @@ int eo_fmm(int ndim, const int64_t* dims, double h, const double* F,
         for (int t = 0; t < c; ++t) {
             int64_t j = nb[t];
             if (acc[j]) continue;
-            double v = tentative(&g, phi, acc, j, node_H(h, F[j]));
+            double v = tentative(&g, phi, acc, j, F[j], h, dsp);
             if (v < phi[j]) {
                 phi[j] = v;
                 rc = heap_push(&hp, v, j);
@@ -332,7 +413,7 @@ int eo_fmm(int ndim, const int64_t* dims, double h, const double* F,
         for (int t = 0; t < c; ++t) {
             int64_t j = nb[t];
             if (acc[j]) continue;
-            double v = tentative(&g, phi, acc, j, node_H(h, F[j]));
+            double v = tentative(&g, phi, acc, j, F[j], h, dsp);
             if (v < phi[j]) {
                 phi[j] = v;
                 rc = heap_push(&hp, v, j);
@@ -345,13 +426,19 @@ int eo_fmm(int ndim, const int64_t* dims, double h, const double* F,
     return rc;
 }
 
+int eo_fmm(int ndim, const int64_t* dims, double h, const double* F,
+           const int64_t* src, const double* val, int64_t nsrc, double* phi,
+           int64_t* accept_order, int64_t* n_accepted) {
+    return eo_fmm_a(ndim, dims, h, NULL, F, src, val, nsrc, phi, accept_order, n_accepted);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Fast sweeping (Gauss-Seidel, 2^d alternating orderings)                    */
 /* ------------------------------------------------------------------------- */
 
-int eo_fsm(int ndim, const int64_t* dims, double h, const double* F,
-           const int64_t* src, const double* val, int64_t nsrc, double* phi,
-           int use_bisect, int64_t max_passes, int64_t* passes_out) {
+int eo_fsm_a(int ndim, const int64_t* dims, double h, const double* dsp, const double* F,
+             const int64_t* src, const double* val, int64_t nsrc, double* phi,
+             int use_bisect, int64_t max_passes, int64_t* passes_out) {
     grid_t g;
     if (grid_init(&g, ndim, dims) || nsrc < 1 || !(h > 0.0)) return EO_BAD;
     unsigned char* fixed = (unsigned char*)malloc((size_t)g.n);
@@ -377,8 +464,8 @@ int eo_fsm(int ndim, const int64_t* dims, double h, const double* F,
                 }
                 if (fixed[i]) continue;
                 axis_mins(&g, phi, i, a);
-                double H = node_H(h, F[i]);
-                double v = use_bisect ? eo_godunov_bisect(g.nd, a, H) : eo_godunov(g.nd, a, H);
+                double v = (use_bisect && !dsp) ? eo_godunov_bisect(g.nd, a, node_H(h, F[i]))
+                                                : local_solve(g.nd, a, F[i], h, dsp);
                 if (v < phi[i]) { phi[i] = v; changed = 1; }
             }
         }
@@ -386,6 +473,12 @@ int eo_fsm(int ndim, const int64_t* dims, double h, const double* F,
     free(fixed);
     if (passes_out) *passes_out = pass;
     return changed ? EO_NOCONV : EO_OK;
+}
+
+int eo_fsm(int ndim, const int64_t* dims, double h, const double* F,
+           const int64_t* src, const double* val, int64_t nsrc, double* phi,
+           int use_bisect, int64_t max_passes, int64_t* passes_out) {
+    return eo_fsm_a(ndim, dims, h, NULL, F, src, val, nsrc, phi, use_bisect, max_passes, passes_out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -535,9 +628,9 @@ int eo_ifim_f(int ndim, const int64_t* dims, double h, const double* F,
 /* ------------------------------------------------------------------------- */
 /* Fast iterative method (Section 2.3)                                        */
 /* ------------------------------------------------------------------------- */
-int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
-           const int64_t* src, const double* sval, int64_t nsrc, double eps,
-           int64_t max_iters, double* phi, int64_t* stats) {
+int eo_fim_a(int ndim, const int64_t* dims, double h, const double* dsp, const double* F,
+             const int64_t* src, const double* sval, int64_t nsrc, double eps,
+             int64_t max_iters, double* phi, int64_t* stats) {
     grid_t g;
     if (grid_init(&g, ndim, dims) || nsrc < 1 || !(h > 0.0)) return EO_BAD;
     int64_t N = g.n;
@@ -574,7 +667,7 @@ int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
         for (int64_t k = 0; k < na; ++k) {
             int64_t i = A[k];
             axis_mins(&g, phi, i, a);
-            val[k] = eo_godunov(g.nd, a, h / F[i]);
+            val[k] = local_solve(g.nd, a, F[i], h, dsp);
         }
         nb = nc = 0;
         for (int64_t k = 0; k < na; ++k) {
@@ -598,7 +691,7 @@ int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
                 if (lab[j] == L_ACTIVE || lab[j] == L_FIXED || !(F[j] > 0.0)) continue;
                 stats[2] += 1;
                 axis_mins(&g, phi, j, a);
-                double q = eo_godunov(g.nd, a, h / F[j]);
+                double q = local_solve(g.nd, a, F[j], h, dsp);
                 if (q < phi[j] - eps) {
                     phi[j] = q;
                     lab[j] = L_ACTIVE;
@@ -611,6 +704,12 @@ int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
 done:
     free(lab); free(A); free(B); free(C); free(val);
     return rc;
+}
+
+int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
+           const int64_t* src, const double* sval, int64_t nsrc, double eps,
+           int64_t max_iters, double* phi, int64_t* stats) {
+    return eo_fim_a(ndim, dims, h, NULL, F, src, sval, nsrc, eps, max_iters, phi, stats);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -636,9 +735,9 @@ static int cmp_desc(const void* x, const void* y) {
     return (i < j) ? -1 : (i > j);
 }
 
-int eo_adjoint(int ndim, const int64_t* dims, double h, const double* F,
-               const int64_t* src, int64_t nsrc, const double* phi,
-               const double* dL_dphi, double* dL_dF, double* lambda_out) {
+int eo_adjoint_a(int ndim, const int64_t* dims, double h, const double* dsp, const double* F,
+                 const int64_t* src, int64_t nsrc, const double* phi,
+                 const double* dL_dphi, double* dL_dF, double* lambda_out) {
     grid_t g;
     if (grid_init(&g, ndim, dims) || nsrc < 1 || !(h > 0.0)) return EO_BAD;
     int64_t N = g.n;
@@ -675,21 +774,50 @@ int eo_adjoint(int ndim, const int64_t* dims, double h, const double* F,
             if (x > 0 && phi[i - g.s[k]] < v) { v = phi[i - g.s[k]]; best = i - g.s[k]; }
             if (x + 1 < g.d[k] && phi[i + g.s[k]] < v) { v = phi[i + g.s[k]]; best = i + g.s[k]; }
             if (best >= 0 && v < pi) {
+                /* per-axis spacing: the equation weighs axis k by 1/dsp_k^2 */
                 jk[nu] = best;
-                wk[nu] = pi - v;
+                wk[nu] = dsp ? (pi - v) / (dsp[k] * dsp[k]) : pi - v;
                 W += wk[nu];
                 ++nu;
             }
         }
         if (nu == 0 || !(W > 0.0)) continue;
-        double H = h / F[i];
         double li = lam[i];
-        dL_dF[i] = -li * H * H / (F[i] * W);
+        if (dsp) {
+            dL_dF[i] = -li / (F[i] * F[i] * F[i] * W);
+        } else {
+            double H = h / F[i];
+            dL_dF[i] = -li * H * H / (F[i] * W);
+        }
         for (int u = 0; u < nu; ++u) lam[jk[u]] += (wk[u] / W) * li;
     }
     free(is_src);
     free(ord);
     if (!lambda_out) free(lam);
+    return EO_OK;
+}
+
+int eo_adjoint(int ndim, const int64_t* dims, double h, const double* F,
+               const int64_t* src, int64_t nsrc, const double* phi,
+               const double* dL_dphi, double* dL_dF, double* lambda_out) {
+    return eo_adjoint_a(ndim, dims, h, NULL, F, src, nsrc, phi, dL_dphi, dL_dF, lambda_out);
+}
+
+/* G_i(phi) with per-axis spacing in float32 arithmetic */
+int eo_apply_local_af(int ndim, const int64_t* dims, const double* dsp, const float* F,
+                      const float* phi, float* out) {
+    grid_t g;
+    if (grid_init(&g, ndim, dims)) return EO_BAD;
+    float a[3], Hk[3];
+    for (int64_t i = 0; i < g.n; ++i) {
+        axis_mins_f(&g, phi, i, a);
+        if (F[i] > 0.0f) {
+            for (int k = 0; k < g.nd; ++k) Hk[k] = (float)dsp[k] / F[i];
+            out[i] = eo_godunov_aniso_f(g.nd, a, Hk);
+        } else {
+            out[i] = INFINITY;
+        }
+    }
     return EO_OK;
 }
 
