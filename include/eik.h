@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 3
+#define EIK_ABI_VERSION 4
 
 typedef enum {
     EIK_OK = 0,
@@ -135,6 +135,11 @@ typedef struct {
     size_t workspace_bytes;
     void* stream;              /* hipStream_t; NULL -> default stream */
     eik_stats* stats;          /* host, nullable */
+    double spacing[3];         /* per-axis grid spacing in dims order (Eq 5 with
+                                  dx != dy, Algorithm 1.2, and its 3D analogue):
+                                  all zero -> the isotropic h argument; else the
+                                  first ndim entries must be finite and > 0 and
+                                  replace h (which must still be valid) */
 } eik_options;
 
 /* Fill *opt with the defaults listed above.  Never fails. */

@@ -41,7 +41,7 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 3
+EIK_ABI_VERSION = 4
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
@@ -99,6 +99,7 @@ class EikOptions(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("stats", ctypes.POINTER(EikStats)),
+        ("spacing", ctypes.c_double * 3),
     ]
 
 
@@ -178,7 +179,7 @@ def _check(rc: int):
 def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[Sequence[int]] = None,
                  inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
                  skip_remedy: bool = False, async_: bool = False, profile: bool = False,
-                 fifo: bool = False) -> EikOptions:
+                 fifo: bool = False, spacing: Optional[Sequence[float]] = None) -> EikOptions:
     o = EikOptions()
     _load().eik_default_options(ctypes.byref(o))
     if dtype is not None:
@@ -196,6 +197,9 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
                (EIK_FLAG_ASYNC if async_ else 0) |
                (EIK_FLAG_PROFILE if profile else 0) |
                (EIK_FLAG_FIFO_REMEDY if fifo else 0))
+    if spacing is not None:
+        for k, v in enumerate(spacing):
+            o.spacing[k] = float(v)
     return o
 
 
@@ -254,11 +258,11 @@ def _sources_array(sources, shape) -> np.ndarray:
     return np.ascontiguousarray(arr.astype(np.int64).ravel())
 
 
-def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = "tile",
+def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[str, int] = "tile",
           source_values=None, deterministic: bool = False, skip_remedy: bool = False,
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
           out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False,
-          async_: bool = False, fifo: bool = False):
+          async_: bool = False, fifo: bool = False, spacing: Optional[Sequence[float]] = None):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
@@ -271,7 +275,8 @@ def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = 
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, async_=async_, profile=profile, fifo=fifo)
+                       skip_remedy, async_=async_, profile=profile, fifo=fifo, spacing=spacing)
+    h = 1.0 if h is None and spacing is not None else h
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     dims = _dims(F.shape)
@@ -302,14 +307,16 @@ def solve(F, h: float, sources, eps: float = 0.0, *, variant: Union[str, int] = 
     return (phi, st.to_dict()) if stats else phi
 
 
-def apply_local(F, phi, h: float, out=None):
-    """out_i = G_i(phi): the exact Godunov local solve at every node."""
+def apply_local(F, phi, h: Optional[float], out=None, spacing: Optional[Sequence[float]] = None):
+    """out_i = G_i(phi): the exact Godunov local solve at every node
+    (spacing: one per axis for dx != dy; h may then be None)."""
     torch = _torch()
     _check_device_tensor(F, "F")
     _check_device_tensor(phi, "phi")
     if phi.shape != F.shape or phi.dtype != F.dtype:
         raise ValueError("phi must match F in shape and dtype")
-    opt = make_options(_dtype_code(F))
+    opt = make_options(_dtype_code(F), spacing=spacing)
+    h = 1.0 if h is None and spacing is not None else h
     opt.stream = torch.cuda.current_stream(F.device).cuda_stream
     res = out if out is not None else torch.empty_like(F)
     dims = _dims(F.shape)
@@ -326,8 +333,9 @@ def eik_adjoint_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] =
                                                   ctypes.byref(opt) if opt is not None else None))
 
 
-def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats: bool = False,
-            stream=None, profile: bool = False, async_: bool = False, max_iters: int = 0):
+def adjoint(F, phi, h: Optional[float], sources, dL_dphi, out=None, workspace=None, stats: bool = False,
+            stream=None, profile: bool = False, async_: bool = False, max_iters: int = 0,
+            spacing: Optional[Sequence[float]] = None):
     """dL/dF at the converged solution phi (same F, h, sources).  async_ as in
     solve()."""
     torch = _torch()
@@ -335,7 +343,8 @@ def adjoint(F, phi, h: float, sources, dL_dphi, out=None, workspace=None, stats:
         _check_device_tensor(t, n)
         if t.shape != F.shape or t.dtype != F.dtype:
             raise ValueError(f"{n} must match F in shape and dtype")
-    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile)
+    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile, spacing=spacing)
+    h = 1.0 if h is None and spacing is not None else h
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     s = stream if stream is not None else torch.cuda.current_stream(F.device)

@@ -92,15 +92,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(BatchGeom<T> bg, const T* _
                     }
                     if (side >= 0 && v < p) {
                         u |= static_cast<uint8_t>((1u << (2 * k)) | (static_cast<uint32_t>(side) << (2 * k + 1)));
-                        w[k] = p - v;
+                        // per-axis spacing weighs axis k by 1 / spacing^2 (axis k = x, y, z
+                        // is dims entry ND - 1 - k)
+                        const T dk = I.d[ND - 1 - k];
+                        w[k] = I.aniso ? (p - v) / (dk * dk) : p - v;
                         W = W + w[k];
                     }
                 }
             }
             T d = T(0);
             if (u && W > T(0)) {
-                const T Hh = I.h / f;
-                d = -(Hh * Hh) / (f * W);
+                if (I.aniso) {
+                    d = -T(1) / (f * f * f * W);
+                } else {
+                    const T Hh = I.h / f;
+                    d = -(Hh * Hh) / (f * W);
+                }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) w[k] = w[k] / W;
             } else {

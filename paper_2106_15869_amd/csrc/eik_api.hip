@@ -87,6 +87,29 @@ static eik_status check_options(const eik_options& o) {
     return EIK_OK;
 }
 
+// Per-axis spacing of opt (all zero: isotropic h).  Fails unless the first
+// ndim entries are all finite and > 0 (or all zero) and the rest zero.
+static eik_status check_spacing(const eik_options& o, int ndim, bool& aniso) {
+    aniso = false;
+    for (int k = 0; k < 3; ++k) aniso |= o.spacing[k] != 0.0;
+    if (!aniso) return EIK_OK;
+    for (int k = 0; k < 3; ++k) {
+        const double v = o.spacing[k];
+        if (k < ndim ? !(v > 0.0 && std::isfinite(v)) : v != 0.0)
+            return fail(EIK_ERR_INVALID_ARGUMENT, "spacing needs ndim finite positive entries (dims order), the rest 0");
+    }
+    return EIK_OK;
+}
+
+template <typename T>
+static Spacing<T> make_spacing(double h, const eik_options& o, bool aniso) {
+    Spacing<T> sp{};
+    sp.h = static_cast<T>(h);
+    sp.aniso = aniso ? 1 : 0;
+    for (int k = 0; k < 3; ++k) sp.d[k] = static_cast<T>(o.spacing[k]);
+    return sp;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
@@ -139,10 +162,11 @@ static Batch single_batch(const Problem& P, const eik_options& o, TileCfg c,
     Batch b;
     b.nd = P.g.nd;
     b.cfg = c;
-    batch_add(b, P.g.nx, P.g.ny, P.g.nz, h);
+    bool aniso = false;
+    for (int k = 0; k < 3; ++k) aniso |= o.spacing[k] != 0.0;
+    batch_add(b, P.g.nx, P.g.ny, P.g.nz, h, aniso ? o.spacing : nullptr);
     b.src = src;
     b.src_inst.assign(src.size(), 0);
-    (void)o;
     return b;
 }
 
@@ -187,7 +211,7 @@ eik_status check_sources(const Problem& P, const int64_t* sources, int64_t n_sou
 }
 
 template <typename T>
-static eik_status solve_nodelist(const Problem& P, const T* F, double h, double eps,
+static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>& hT, double eps,
                                  const std::vector<std::pair<int, double>>& src, T* phi,
                                  const eik_options& o, char* ws, hipStream_t s, eik_stats* st) {
     const bool det = (o.flags & EIK_FLAG_DETERMINISTIC) != 0;
@@ -224,7 +248,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, double h, double 
         }));
     launched += 1 + 2 * static_cast<int64_t>(batches.size());
 
-    const T hT = static_cast<T>(h), eT = static_cast<T>(eps);
+    const T eT = static_cast<T>(eps);
     auto iter_args = [&](int64_t t, bool first) {
         NodeIter<T> a{};
         a.F = F;
@@ -332,6 +356,8 @@ EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, d
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(EIK_ERR_INVALID_ARGUMENT, "eps must be finite and >= 0");
     if ((rc = check_sources(P, sources, n_sources, o.source_values))) return rc;
     if (F == phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_out must not alias F");
+    bool aniso = false;
+    if ((rc = check_spacing(o, ndim, aniso))) return rc;
 
     const size_t need = workspace_bytes(P, o);
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -355,9 +381,9 @@ EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, d
                                  o.stats);
     }
     if (o.dtype == EIK_FLOAT64)
-        return solve_nodelist<double>(P, static_cast<const double*>(F), h, eps, src,
+        return solve_nodelist<double>(P, static_cast<const double*>(F), make_spacing<double>(h, o, aniso), eps, src,
                                       static_cast<double*>(phi_out), o, ws, s, o.stats);
-    return solve_nodelist<float>(P, static_cast<const float*>(F), h, eps, src,
+    return solve_nodelist<float>(P, static_cast<const float*>(F), make_spacing<float>(h, o, aniso), eps, src,
                                  static_cast<float*>(phi_out), o, ws, s, o.stats);
 }
 
@@ -373,14 +399,16 @@ EIK_API eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim,
     if (!F || !phi || !out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
     if (out == phi || out == F) return fail(EIK_ERR_INVALID_ARGUMENT, "out must not alias the inputs");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+    bool aniso = false;
+    if ((rc = check_spacing(o, ndim, aniso))) return rc;
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     if (o.dtype == EIK_FLOAT64)
         HIP_TRY(launch_apply_local<double>(P.g, static_cast<const double*>(F),
-                                           static_cast<const double*>(phi), h,
+                                           static_cast<const double*>(phi), make_spacing<double>(h, o, aniso),
                                            static_cast<double*>(out), s));
     else
         HIP_TRY(launch_apply_local<float>(P.g, static_cast<const float*>(F),
-                                          static_cast<const float*>(phi), static_cast<float>(h),
+                                          static_cast<const float*>(phi), make_spacing<float>(h, o, aniso),
                                           static_cast<float*>(out), s));
     if (!(o.flags & EIK_FLAG_ASYNC)) HIP_TRY(hipStreamSynchronize(s));
     return EIK_OK;
@@ -408,6 +436,8 @@ EIK_API eik_status eik_adjoint(const void* F, const void* phi, int32_t ndim, con
         return fail(EIK_ERR_INVALID_ARGUMENT, "dL_dF_out must not alias the inputs");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
     if ((rc = check_sources(P, sources, n_sources, nullptr))) return rc;
+    bool aniso = false;
+    if ((rc = check_spacing(o, ndim, aniso))) return rc;
     auto src = dedupe_sources(sources, nullptr, n_sources);
     const Batch b = single_batch(P, o, pick_tile(P.g.nd, o), src, h);
     const size_t need = adjoint_workspace_bytes(b, elem_size(o.dtype));
@@ -460,7 +490,7 @@ static eik_status make_batch(int32_t ndim, const eik_instance* inst, int32_t n_i
         if (d[0] >= (int64_t(1) << 31) || d[1] >= (int64_t(1) << 31) || d[2] >= (int64_t(1) << 31) ||
             b.n + n >= (int64_t(1) << 31))
             return fail(EIK_ERR_INVALID_ARGUMENT, "a batch must have < 2^31 nodes");
-        batch_add(b, static_cast<int>(d[2]), static_cast<int>(d[1]), static_cast<int>(d[0]), e.h);
+        batch_add(b, static_cast<int>(d[2]), static_cast<int>(d[1]), static_cast<int>(d[0]), e.h, nullptr);
         nsrc += e.n_sources;
     }
     if (!sources) return EIK_OK;
@@ -494,6 +524,8 @@ static eik_status make_batch(int32_t ndim, const eik_instance* inst, int32_t n_i
 static eik_status batch_options(const eik_options& o) {
     eik_status rc = check_options(o);
     if (rc) return rc;
+    if (o.spacing[0] != 0.0 || o.spacing[1] != 0.0 || o.spacing[2] != 0.0)
+        return fail(EIK_ERR_UNSUPPORTED, "batched solves take one isotropic spacing per instance");
     if (o.variant != EIK_VARIANT_TILE)
         return fail(EIK_ERR_UNSUPPORTED, "batched solves use the tile variant");
     return EIK_OK;
@@ -557,6 +589,8 @@ EIK_API eik_status eik_adjoint_batch(const void* F, const void* phi, int32_t ndi
     eik_options o = resolve(opt);
     eik_status rc = check_options(o);
     if (rc) return rc;
+    if (o.spacing[0] != 0.0 || o.spacing[1] != 0.0 || o.spacing[2] != 0.0)
+        return fail(EIK_ERR_UNSUPPORTED, "batched solves take one isotropic spacing per instance");
     if (!F || !phi || !dL_dphi || !dL_dF_out) return fail(EIK_ERR_INVALID_ARGUMENT, "null array argument");
     if (dL_dF_out == F || dL_dF_out == phi || dL_dF_out == dL_dphi)
         return fail(EIK_ERR_INVALID_ARGUMENT, "dL_dF_out must not alias the inputs");

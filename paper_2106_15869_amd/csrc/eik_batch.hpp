@@ -49,6 +49,8 @@ Inst<T> device_inst(const HostInst& h) {
     d.node_base = h.node_base;
     d.tile_base = h.tile_base;
     d.h = static_cast<T>(h.h);
+    for (int k = 0; k < 3; ++k) d.d[k] = static_cast<T>(h.d[k]);
+    d.aniso = h.aniso;
     return d;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "eik_internal.hpp"
+
 namespace eik {
 
 // Node labels (one byte per node).  FAR: never reached; ACTIVE: in the update
@@ -94,10 +96,65 @@ template <typename T> __device__ __forceinline__ T cell_H(T h, T f) {
     return f > T(0) ? h / f : pos_inf<T>();
 }
 
+// Per-axis spacing (Eq 5 with dx != dy, the case of Algorithm 1.2, and its 3D
+// analogue): the root of sum_k ((phi - a_k)^+ / H_k)^2 = 1 with
+// H_k = spacing_k / F.  Same progressive rule on the minima sorted ascending
+// (a stable sort; each H_k travels with its a_k), in shifted form: with
+// t = phi - a_1, b_k = a_k - a_1 and w_k = 1 / H_k^2 the active axes give
+// A t^2 - 2 B t + C = 0, A = sum w_k, B = sum w_k b_k, C = sum w_k b_k^2 - 1.
+template <typename T, int ND>
+__device__ __forceinline__ T godunov_aniso(T a0, T a1, T a2, T H0, T H1, T H2) {
+    const T inf = pos_inf<T>();
+    if (a1 < a0) {
+        T t = a0; a0 = a1; a1 = t;
+        t = H0; H0 = H1; H1 = t;
+    }
+    if (ND == 3 && a2 < a1) {
+        T t = a1; a1 = a2; a2 = t;
+        t = H1; H1 = H2; H2 = t;
+        if (a1 < a0) {
+            t = a0; a0 = a1; a1 = t;
+            t = H0; H0 = H1; H1 = t;
+        }
+    }
+    if (!(a0 < inf) || !(H0 < inf)) return inf;
+    T phi = a0 + H0;
+    if (!(phi > a1)) return phi;
+    T A = T(1) / (H0 * H0);
+    T b = a1 - a0;
+    T w = T(1) / (H1 * H1);
+    A = A + w;
+    T B = w * b;
+    T C = T(-1) + w * b * b;
+    T disc = B * B - A * C;
+    disc = disc < T(0) ? T(0) : disc;
+    phi = a0 + (B + dev_sqrt(disc)) / A;
+    if (ND == 3) {
+        if (!(phi > a2)) return phi;
+        b = a2 - a0;
+        w = T(1) / (H2 * H2);
+        A = A + w;
+        B = B + w * b;
+        C = C + w * b * b;
+        disc = B * B - A * C;
+        disc = disc < T(0) ? T(0) : disc;
+        phi = a0 + (B + dev_sqrt(disc)) / A;
+    }
+    return phi;
+}
+
+// G_i from the per-axis minima (dims order) and the node's speed.
+template <typename T, int ND>
+__device__ __forceinline__ T local_solve(T a0, T a1, T a2, T f, const Spacing<T>& sp) {
+    if (!sp.aniso) return godunov<T, ND>(a0, a1, a2, cell_H(sp.h, f));
+    if (!(f > T(0))) return pos_inf<T>();
+    return godunov_aniso<T, ND>(a0, a1, a2, sp.d[0] / f, sp.d[1] / f, ND == 3 ? sp.d[2] / f : pos_inf<T>());
+}
+
 // G_i(phi) from global memory.
 template <typename T, int ND>
 __device__ __forceinline__ T eval_node(const T* phi, const T* F, const Grid& g, int i, int x, int y,
-                                       int z, T h) {
+                                       int z, const Spacing<T>& sp) {
     const T inf = pos_inf<T>();
     T ax = inf, ay = inf, az = inf;
     if (x > 0) ax = phi[i - 1];
@@ -108,8 +165,8 @@ __device__ __forceinline__ T eval_node(const T* phi, const T* F, const Grid& g, 
         if (z > 0) az = phi[i - g.sxy];
         if (z + 1 < g.nz) az = tmin(az, phi[i + g.sxy]);
     }
-    if (ND == 2) return godunov<T, 2>(ay, ax, inf, cell_H(h, F[i]));
-    return godunov<T, 3>(az, ay, ax, cell_H(h, F[i]));
+    if (ND == 2) return local_solve<T, 2>(ay, ax, inf, F[i], sp);
+    return local_solve<T, 3>(az, ay, ax, F[i], sp);
 }
 
 // ---------------------------------------------------------------------------

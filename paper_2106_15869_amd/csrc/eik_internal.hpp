@@ -10,6 +10,15 @@ namespace eik {
 
 struct Grid;
 
+// Grid spacing: isotropic h, or per-axis spacing d[k] (dims order: z, y, x in
+// 3D; y, x in 2D) when aniso is set.
+template <typename T>
+struct Spacing {
+    T h;
+    T d[3];
+    int aniso;
+};
+
 // Device control block (lives in the workspace).
 struct Ctl {
     int cnt[4];       // spare counters
@@ -84,6 +93,8 @@ struct Inst {
     int node_base;   // flat index of the grid's first node in F / phi / labels
     int tile_base;   // id of its first tile
     T h;
+    T d[3];          // per-axis spacing (dims order) when aniso
+    int aniso;
 };
 
 // Batch-wide tile geometry handed to every tile kernel.
@@ -114,20 +125,20 @@ template <typename T>
 hipError_t launch_seed_active(const GridDims& g, const T* F, uint8_t* lab, const SrcBatch<T>& b,
                               const SegList& out, int seg, hipStream_t s);
 template <typename T>
-hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
+hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, bool det, hipStream_t s);
 template <typename T>
-hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, T h, T eps,
+hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, const Spacing<T>& h, T eps,
                          const SegList& out, hipStream_t s);
 template <typename T>
-hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s);
+hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, bool det, hipStream_t s);
 hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s);
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_words(void* p, size_t n, uint32_t v, hipStream_t s);  // n 32-bit words
 template <typename T>
-hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
+hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, const Spacing<T>& h, T* out,
                               hipStream_t s);
 template <typename T>
-hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, T h, T eps, hipStream_t s);
+hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, hipStream_t s);
 hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
 

@@ -204,7 +204,7 @@ __device__ __forceinline__ int list_prologue(const NodeIter<T>& a, int* s_pref, 
 }
 
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T h, T eps) {
+__global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, Spacing<T> sp, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
     __shared__ int s_w;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T 
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pi = a.phi[i];
-            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, sp);
             mask = step2_apply_node<T, ND>(a, g, i, pi, pt, eps, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(NodeIter<T> a, GridDims gd, T 
 }
 
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_step2_eval(NodeIter<T> a, GridDims gd, T h) {
+__global__ __launch_bounds__(kBlock) void k_step2_eval(NodeIter<T> a, GridDims gd, Spacing<T> sp) {
     __shared__ int s_pref[G + 1];
     const Grid g = make_grid(gd);
     int lo, hi;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_step2_eval(NodeIter<T> a, GridDims g
         const int i = seg_entry<G>(a.cur, s_pref, k);
         int x, y, z;
         decode<ND>(g, i, x, y, z);
-        a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+        a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, sp);
     }
 }
 
@@ -280,8 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_step2_apply(NodeIter<T> a, GridDims 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_detect(GridDims gd, const T* __restrict__ F,
                                                    const T* __restrict__ phi,
-                                                   const uint8_t* __restrict__ lab, T h, T eps,
-                                                   SegList out) {
+                                                   const uint8_t* __restrict__ lab, Spacing<T> sp,
+                                                   T eps, SegList out) {
     __shared__ int s_cnt;
     const Grid g = make_grid(gd);
     SegAppender app{&s_cnt};
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_detect(GridDims gd, const T* __restr
         if (i < hi && lab[i] != L_FIXED) {
             int x, y, z;
             decode<ND>(g, i, x, y, z);
-            const T pt = eval_node<T, ND>(phi, F, g, i, x, y, z, h);
+            const T pt = eval_node<T, ND>(phi, F, g, i, x, y, z, sp);
             mask = pt < phi[i] - eps ? 1u : 0u;
         }
         app.push_mask<1>(out, items, mask);
@@ -348,7 +348,7 @@ __device__ __forceinline__ uint32_t remedy_tag(const NodeIter<T>& a, bool advanc
 }
 
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T h, T eps) {
+__global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, Spacing<T> sp, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
     __shared__ int s_w;
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T
             const int i = seg_entry<G>(a.cur, s_pref, k);
             int x, y, z;
             decode<ND>(g, i, x, y, z);
-            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, sp);
             mask = remedy_apply_node<T, ND>(a, g, i, a.phi[i], pt, eps, tag, items, written);
         }
         app.push_mask<7>(a.next, items, mask);
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_remedy(NodeIter<T> a, GridDims gd, T
 }
 
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_remedy_eval(NodeIter<T> a, GridDims gd, T h) {
+__global__ __launch_bounds__(kBlock) void k_remedy_eval(NodeIter<T> a, GridDims gd, Spacing<T> sp) {
     __shared__ int s_pref[G + 1];
     const Grid g = make_grid(gd);
     remedy_tag(a, true);
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_remedy_eval(NodeIter<T> a, GridDims 
         const int i = seg_entry<G>(a.cur, s_pref, k);
         int x, y, z;
         decode<ND>(g, i, x, y, z);
-        a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+        a.vals[k] = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, sp);
     }
 }
 
@@ -457,7 +457,7 @@ __device__ __forceinline__ void atomic_min_value(double* p, double v) {
 }
 
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_fim_update(NodeIter<T> a, GridDims gd, T h, T eps) {
+__global__ __launch_bounds__(kBlock) void k_fim_update(NodeIter<T> a, GridDims gd, Spacing<T> sp, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt, s_cnt_conv;
     __shared__ int s_w;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_fim_update(NodeIter<T> a, GridDims g
             int x, y, z;
             decode<ND>(g, i, x, y, z);
             const T pi = a.phi[i];
-            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, h);
+            const T pt = eval_node<T, ND>(a.phi, a.F, g, i, x, y, z, sp);
             if (pt < inf && pi - pt <= eps) {
                 label_add(a.lab, i, int(L_CONV) - int(L_ACTIVE));
                 mconv = 1u;
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_fim_update(NodeIter<T> a, GridDims g
 // Reads the converged list of this iteration and appends to the active list
 // after the entries k_fim_update published there.
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_fim_check(NodeIter<T> a, GridDims gd, T h, T eps) {
+__global__ __launch_bounds__(kBlock) void k_fim_check(NodeIter<T> a, GridDims gd, Spacing<T> sp, T eps) {
     __shared__ int s_pref[G + 1];
     __shared__ int s_cnt;
     __shared__ int s_w, s_e;
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_fim_check(NodeIter<T> a, GridDims gd
                 int qx, qy, qz;
                 decode<ND>(g, q, qx, qy, qz);
                 ++evals;
-                const T pt = eval_node<T, ND>(a.phi, a.F, g, q, qx, qy, qz, h);
+                const T pt = eval_node<T, ND>(a.phi, a.F, g, q, qx, qy, qz, sp);
                 if (pt < a.phi[q] - eps) {
                     atomic_min_value(a.phi + q, pt);
                     ++written;
@@ -554,13 +554,13 @@ __global__ __launch_bounds__(kBlock) void k_fim_check(NodeIter<T> a, GridDims gd
 
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_apply_local(GridDims gd, const T* __restrict__ F,
-                                                        const T* __restrict__ phi, T h,
+                                                        const T* __restrict__ phi, Spacing<T> sp,
                                                         T* __restrict__ out) {
     const Grid g = make_grid(gd);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.n; i += gridDim.x * kBlock) {
         int x, y, z;
         decode<ND>(g, i, x, y, z);
-        out[i] = eval_node<T, ND>(phi, F, g, i, x, y, z, h);
+        out[i] = eval_node<T, ND>(phi, F, g, i, x, y, z, sp);
     }
 }
 
@@ -637,7 +637,7 @@ hipError_t launch_seg_clear(int* count, int nseg, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s) {
+hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, bool det, hipStream_t s) {
     if (det) {
         if (g.nd == 2) {
             hipLaunchKernelGGL((k_step2_eval<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h);
@@ -656,7 +656,7 @@ hipError_t launch_step2(const GridDims& g, const NodeIter<T>& it, T h, T eps, bo
 }
 
 template <typename T>
-hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, T h, T eps,
+hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint8_t* lab, const Spacing<T>& h, T eps,
                          const SegList& out, hipStream_t s) {
     if (g.nd == 2)
         hipLaunchKernelGGL((k_detect<T, 2>), dim3(G), dim3(kBlock), 0, s, g, F, phi, lab, h, eps, out);
@@ -666,7 +666,7 @@ hipError_t launch_detect(const GridDims& g, const T* F, const T* phi, const uint
 }
 
 template <typename T>
-hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, bool det, hipStream_t s) {
+hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, bool det, hipStream_t s) {
     if (det) {
         if (g.nd == 2) {
             hipLaunchKernelGGL((k_remedy_eval<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h);
@@ -685,7 +685,7 @@ hipError_t launch_remedy(const GridDims& g, const NodeIter<T>& it, T h, T eps, b
 }
 
 template <typename T>
-hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, T* out,
+hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, const Spacing<T>& h, T* out,
                               hipStream_t s) {
     if (g.nd == 2)
         hipLaunchKernelGGL((k_apply_local<T, 2>), dim3(dense_blocks(g.n)), dim3(kBlock), 0, s, g, F,
@@ -697,7 +697,7 @@ hipError_t launch_apply_local(const GridDims& g, const T* F, const T* phi, T h, 
 }
 
 template <typename T>
-hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, T h, T eps, hipStream_t s) {
+hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, hipStream_t s) {
     if (g.nd == 2) {
         hipLaunchKernelGGL((k_fim_update<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
         hipLaunchKernelGGL((k_fim_check<T, 2>), dim3(G), dim3(kBlock), 0, s, it, g, h, eps);
@@ -723,15 +723,15 @@ hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
     template hipError_t launch_seed<T>(T*, uint8_t*, const SrcBatch<T>&, hipStream_t);             \
     template hipError_t launch_seed_active<T>(const GridDims&, const T*, uint8_t*,                 \
                                               const SrcBatch<T>&, const SegList&, int, hipStream_t); \
-    template hipError_t launch_step2<T>(const GridDims&, const NodeIter<T>&, T, T, bool,           \
-                                        hipStream_t);                                              \
-    template hipError_t launch_detect<T>(const GridDims&, const T*, const T*, const uint8_t*, T, T, \
-                                         const SegList&, hipStream_t);                             \
-    template hipError_t launch_remedy<T>(const GridDims&, const NodeIter<T>&, T, T, bool,          \
-                                         hipStream_t);                                             \
-    template hipError_t launch_apply_local<T>(const GridDims&, const T*, const T*, T, T*,          \
-                                              hipStream_t);                                        \
-    template hipError_t launch_fim<T>(const GridDims&, const NodeIter<T>&, T, T, hipStream_t);
+    template hipError_t launch_step2<T>(const GridDims&, const NodeIter<T>&, const Spacing<T>&, T,  \
+                                        bool, hipStream_t);                                        \
+    template hipError_t launch_detect<T>(const GridDims&, const T*, const T*, const uint8_t*,       \
+                                         const Spacing<T>&, T, const SegList&, hipStream_t);       \
+    template hipError_t launch_remedy<T>(const GridDims&, const NodeIter<T>&, const Spacing<T>&, T, \
+                                         bool, hipStream_t);                                       \
+    template hipError_t launch_apply_local<T>(const GridDims&, const T*, const T*, const Spacing<T>&, \
+                                              T*, hipStream_t);                                    \
+    template hipError_t launch_fim<T>(const GridDims&, const NodeIter<T>&, const Spacing<T>&, T, hipStream_t);
 
 EIK_INST(float)
 EIK_INST(double)

@@ -120,6 +120,23 @@ struct Shape {
     static constexpr int SZ = LX * LY;
 };
 
+// Per-node value kept in LDS for the local solve: H = h / F (+inf on a
+// barrier), or with per-axis spacing the speed F itself (0 on a barrier).
+template <typename T, bool AN>
+__device__ __forceinline__ T cell_value(const Inst<T>& g, T f) {
+    if (AN) return f > T(0) ? f : T(0);
+    return cell_H(g.h, f);
+}
+template <typename T, bool AN>
+__device__ __forceinline__ T dead_value() {
+    return AN ? T(0) : pos_inf<T>();
+}
+// whether the node can take a finite value (not a barrier, inside the grid)
+template <typename T, bool AN>
+__device__ __forceinline__ bool cell_live(T v) {
+    return AN ? v > T(0) : v < pos_inf<T>();
+}
+
 // Per-lane description of the nodes a lane owns in the current tile.
 template <typename T, int NPT>
 struct Owned {
@@ -164,7 +181,7 @@ __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, 
     }
 }
 
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 __device__ __forceinline__ void own_nodes(const Inst<T>& g, int x0, int y0, int z0, const T* F,
                                           Owned<T, Shape<ND, TX, TY, TZ>::NPT>& o) {
     using S = Shape<ND, TX, TY, TZ>;
@@ -196,21 +213,31 @@ __device__ __forceinline__ void own_nodes(const Inst<T>& g, int x0, int y0, int 
             if (z == TZ - 1 && gz + 1 < g.nz) f |= 32;
         }
         o.face[r] = f;
-        o.H[r] = pos_inf<T>();
-        if (o.ok[r]) o.H[r] = cell_H(g.h, F[o.G[r]]);
+        o.H[r] = dead_value<T, AN>();
+        if (o.ok[r]) o.H[r] = cell_value<T, AN>(g, F[o.G[r]]);
     }
 }
 
 // G_i from the LDS tile (halo holds +inf outside the grid).
-template <typename T, int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ T eval_lds(const T* sphi, int L, T H) {
+// v is the node's H = h / F (isotropic) or its speed F (AN: per-axis spacing,
+// H_k = spacing_k / F); see cell_value.
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
+__device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& g) {
     using S = Shape<ND, TX, TY, TZ>;
+    const T inf = pos_inf<T>();
     const T ax = tmin(sphi[L - 1], sphi[L + 1]);
     const T ay = tmin(sphi[L - S::SY], sphi[L + S::SY]);
-    if (ND == 2) return godunov<T, 2>(ay, ax, pos_inf<T>(), H);
+    if (AN) {
+        if (!(v > T(0))) return inf;
+        if (ND == 2) return godunov_aniso<T, 2>(ay, ax, inf, g.d[0] / v, g.d[1] / v, inf);
+        const T az = tmin(sphi[L - S::SZ], sphi[L + S::SZ]);
+        return godunov_aniso<T, 3>(az, ay, ax, g.d[0] / v, g.d[1] / v, g.d[2] / v);
+    }
+    if (ND == 2) return godunov<T, 2>(ay, ax, inf, v);
     const T az = tmin(sphi[L - S::SZ], sphi[L + S::SZ]);
-    return godunov<T, 3>(az, ay, ax, H);
+    return godunov<T, 3>(az, ay, ax, v);
 }
+
 
 template <int ND, int TX, int TY, int TZ>
 __device__ __forceinline__ int lds_offset(int d) {
@@ -418,7 +445,7 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 // ---------------------------------------------------------------------------
 // STEP 2 on tiles
 // ---------------------------------------------------------------------------
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
@@ -458,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
             G[r] = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
             if (nn < S::NT) {
-                sH[nn] = ok[r] ? cell_H(g.h, a.F[G[r]]) : inf;
+                sH[nn] = ok[r] ? cell_value<T, AN>(g, a.F[G[r]]) : dead_value<T, AN>();
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
             }
@@ -476,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
         for (int r = 0; r < S::NPT; ++r) {
             lab0[r] = ok[r] ? sl[L[r]] : uint8_t(0);
             phi0[r] = ok[r] ? sphi[L[r]] : inf;
-            if (ok[r] && sH[threadIdx.x + r * kBlock] < inf) sl[L[r]] = lab0[r] | kPass;
+            if (ok[r] && cell_live<T, AN>(sH[threadIdx.x + r * kBlock])) sl[L[r]] = lab0[r] | kPass;
         }
         __syncthreads();
         // initial active list: active nodes, and FAR nodes next to a converged
@@ -520,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
                 int x, y, z, Lq;
                 node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
                 ++my_evals;
-                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
                 const T cur = sphi[Lq];
                 if (pt < inf && cur - pt <= eps) {
                     // converged: joins Source; FAR neighbours become active
@@ -591,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
 // ---------------------------------------------------------------------------
 // STEP 3: whole-grid detection, one workgroup per tile
 // ---------------------------------------------------------------------------
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom<T> bg, T eps) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
@@ -606,14 +633,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
         if (threadIdx.x == 0) s_key = kNoKey;  // ordered below the staging barrier
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         Owned<T, S::NPT> o;
-        own_nodes<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, o);
+        own_nodes<T, ND, TX, TY, TZ, AN>(g, x0, y0, z0, a.F, o);
         __syncthreads();
         bool flag = false;
         T low = pos_inf<T>();
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
-            const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, o.L[r], o.H[r]);
+            const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, o.L[r], o.H[r], g);
             if (pt < sphi[o.L[r]] - eps) {
                 flag = true;
                 low = tmin(low, pt);
@@ -640,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
 // Occupancy matters more than a few spilled registers here: the inner
 // iterations are latency-bound, and more resident workgroups hide it (float
 // tiles of up to 512 nodes: eight waves per SIMD measured fastest).
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::NPT <= 2) ? 8 : 1) void k_tile_remedy(
     TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
@@ -710,7 +737,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
                 node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
                 const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
                 const int G = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
-                sH[nn] = ok ? cell_H(g.h, a.F[G]) : inf;
+                sH[nn] = ok ? cell_value<T, AN>(g, a.F[G]) : dead_value<T, AN>();
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
                 tl.dirty[nn] = 0;
@@ -735,7 +762,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
             int x, y, z, L;
             node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
             const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
-            const bool live = sH[nn] < inf && (sl[L] & 3u) != L_FIXED;
+            const bool live = cell_live<T, AN>(sH[nn]) && (sl[L] & 3u) != L_FIXED;
             if (live && ((m & kAllFaces) || (E & static_cast<int>(m))))
                 tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
         }
@@ -760,7 +787,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
                 int x, y, z, Lq;
                 node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
                 ++my_evals;
-                const T pt = eval_lds<T, ND, TX, TY, TZ>(sphi, Lq, sH[q]);
+                const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
                 if (pt < sphi[Lq] - eps) {
                     sphi[Lq] = pt;
                     tl.dirty[q] = 1;
@@ -955,18 +982,18 @@ TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t i
     return w;
 }
 
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 struct TileKernels {
     static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
     static hipError_t detect(const TileIter<T>& a, const BatchGeom<T>& g, T eps, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps);
+        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps);
         return hipGetLastError();
     }
     static hipError_t remedy(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
+        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
 };
@@ -978,18 +1005,24 @@ struct TileOps {
     hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
 };
 
-template <typename T, int ND, int TX, int TY, int TZ>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN = false>
 TileOps<T> ops_of() {
     TileOps<T> k;
-    k.update = &TileKernels<T, ND, TX, TY, TZ>::update;
-    k.detect = &TileKernels<T, ND, TX, TY, TZ>::detect;
-    k.remedy = &TileKernels<T, ND, TX, TY, TZ>::remedy;
+    k.update = &TileKernels<T, ND, TX, TY, TZ, AN>::update;
+    k.detect = &TileKernels<T, ND, TX, TY, TZ, AN>::detect;
+    k.remedy = &TileKernels<T, ND, TX, TY, TZ, AN>::remedy;
     return k;
 }
 
-// Supported tile shapes (z, y, x).
+// Supported tile shapes (z, y, x); per-axis spacing only with the default
+// shapes (32 x 32 in 2D, 8^3 in 3D).
 template <typename T>
-bool select_ops(int nd, const TileCfg& c, TileOps<T>& k) {
+bool select_ops(int nd, const TileCfg& c, bool aniso, TileOps<T>& k) {
+    if (aniso) {
+        if (nd == 2 && c.ty == 32 && c.tx == 32) return k = ops_of<T, 2, 32, 32, 1, true>(), true;
+        if (nd == 3 && c.tz == 8 && c.ty == 8 && c.tx == 8) return k = ops_of<T, 3, 8, 8, 8, true>(), true;
+        return false;
+    }
     if (nd == 2) {
         if (c.ty == 16 && c.tx == 16) return k = ops_of<T, 2, 16, 16, 1>(), true;
         if (c.ty == 32 && c.tx == 32) return k = ops_of<T, 2, 32, 32, 1>(), true;
@@ -1019,8 +1052,8 @@ TileCfg pick_tile(int nd, const eik_options& o) {
     return c;
 }
 
-void batch_add(Batch& b, int nx, int ny, int nz, double h) {
-    HostInst e;
+void batch_add(Batch& b, int nx, int ny, int nz, double h, const double* d) {
+    HostInst e{};
     e.nx = nx;
     e.ny = ny;
     e.nz = nz;
@@ -1030,6 +1063,8 @@ void batch_add(Batch& b, int nx, int ny, int nz, double h) {
     e.node_base = static_cast<int>(b.n);
     e.tile_base = static_cast<int>(b.ntiles);
     e.h = h;
+    e.aniso = d ? 1 : 0;
+    for (int k = 0; k < 3; ++k) e.d[k] = d ? d[k] : 0.0;
     b.inst.push_back(e);
     b.n += static_cast<int64_t>(nx) * ny * nz;
     b.ntiles += static_cast<int64_t>(e.ntx) * e.nty * e.ntz;
@@ -1039,7 +1074,7 @@ Batch with_tiles(const Batch& b, const TileCfg& c) {
     Batch r;
     r.nd = b.nd;
     r.cfg = c;
-    for (const HostInst& e : b.inst) batch_add(r, e.nx, e.ny, e.nz, e.h);
+    for (const HostInst& e : b.inst) batch_add(r, e.nx, e.ny, e.nz, e.h, e.aniso ? e.d : nullptr);
     r.src = b.src;
     r.src_inst = b.src_inst;
     return r;
@@ -1056,7 +1091,9 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
     const TileCfg c = b.cfg;
     TileOps<T> k;
-    if (!select_ops<T>(b.nd, c, k)) return fail(EIK_ERR_INVALID_ARGUMENT, "unsupported tile shape");
+    if (!select_ops<T>(b.nd, c, b.inst[0].aniso != 0, k))
+        return fail(EIK_ERR_INVALID_ARGUMENT, b.inst[0].aniso ? "per-axis spacing needs the default tile shape"
+                                                              : "unsupported tile shape");
     TileWs w = tile_layout(ws, b.n, b.ntiles, b.inst.size(), sizeof(Inst<T>));
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * b.n + 64;
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);

@@ -22,6 +22,8 @@ struct HostInst {
     int ntx, nty, ntz;
     int node_base, tile_base;
     double h;
+    double d[3];  // per-axis spacing in dims order when aniso
+    int aniso;
 };
 
 // Instances laid out back to back in F / phi: instance k's nodes start where
@@ -38,9 +40,9 @@ struct Batch {
 
 TileCfg pick_tile(int nd, const eik_options& o);
 
-// Append an instance of extents (nz, ny, nx) (nz = 1 in 2D) and spacing h,
-// tiled with b.cfg.
-void batch_add(Batch& b, int nx, int ny, int nz, double h);
+// Append an instance of extents (nz, ny, nx) (nz = 1 in 2D) and spacing h
+// (or per-axis spacing `d` in dims order when not NULL), tiled with b.cfg.
+void batch_add(Batch& b, int nx, int ny, int nz, double h, const double* d);
 
 // The same instances and sources tiled with c.
 Batch with_tiles(const Batch& b, const TileCfg& c);

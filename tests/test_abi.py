@@ -52,7 +52,7 @@ def test_default_options(lib):
 
 def test_options_struct_layout():
     # mirrors eik_options in include/eik.h on LP64
-    assert ctypes.sizeof(eik.EikOptions) == 80
+    assert ctypes.sizeof(eik.EikOptions) == 104
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
     assert ctypes.sizeof(eik.EikStats) == 120 + 80
@@ -64,16 +64,17 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "eik.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options), sizeof(eik_stats),'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options), sizeof(eik_stats),'
         ' offsetof(eik_options, max_iters), offsetof(eik_options, stats), offsetof(eik_stats, evals_check),'
-        ' offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms)); return 0; }\n')
+        ' offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms), offsetof(eik_options, spacing));'
+        ' return 0; }\n')
     exe = tmp_path / "layout"
     import subprocess
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(eik.EikOptions), ctypes.sizeof(eik.EikStats), eik.EikOptions.max_iters.offset,
             eik.EikOptions.stats.offset, eik.EikStats.evals_check.offset, eik.EikStats.kernel_launches.offset,
-            eik.EikStats.kernel_ms.offset]
+            eik.EikStats.kernel_ms.offset, eik.EikOptions.spacing.offset]
     assert got == want
 
 
@@ -254,3 +255,27 @@ def test_tune_validation(lib):
     o = eik.make_options(eik.EIK_FLOAT32, "tile")
     assert lib.eik_tune(0x1000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0.0, None, ctypes.byref(o), None, 0,
                         None) == eik.EIK_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("sp,ok", [((0.5, 2.0, 0.0), True), ((0.5, -1.0, 0.0), False), ((0.5, 0.0, 0.0), False),
+                                   ((0.5, 1.0, 3.0), False), ((float("inf"), 1.0, 0.0), False)])
+def test_spacing_validation(lib, sp, ok):
+    """2D problems take two positive spacings (dims order) and a zero third;
+    an invalid combination is rejected before any device work."""
+    o = eik.make_options(eik.EIK_FLOAT32, "node", spacing=sp)
+    # a too-small workspace stops a valid call right after validation, before
+    # any device work
+    o.workspace = 0x100000
+    o.workspace_bytes = 16
+    rc = _solve_raw(lib, (4, 4), opt=o)
+    if ok:
+        assert rc == eik.EIK_ERR_OUT_OF_MEMORY
+    else:
+        assert rc == eik.EIK_ERR_INVALID_ARGUMENT and "spacing" in lib.eik_last_error().decode()
+
+
+def test_spacing_rejected_for_batches(lib):
+    o = eik.make_options(eik.EIK_FLOAT32, "tile", spacing=(1.0, 2.0))
+    src = np.array([0], dtype=np.int64)
+    rc = lib.eik_solve_batch(0x1000, 2, _inst([(8, 8)]), 1, src.ctypes.data, 0.0, 0x2000, ctypes.byref(o))
+    assert rc == eik.EIK_ERR_UNSUPPORTED
