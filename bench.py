@@ -47,7 +47,59 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip adjoint and node-list timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for scaling HBM counters)")
+    ap.add_argument("--replay", action="store_true",
+                    help="instead: the paper's Examples 1, 2, 3, 5 at 200^2 .. 4000^2 with every schedule")
     return ap.parse_args()
+
+
+# The paper's own timings (seconds; Tables 1, 2, 3, 5; improved method and FIM
+# on its GPU), quoted as context for the replay, not as a target.
+PAPER_SECONDS = {
+    1: {"ifim": (0.00141, 0.00384, 0.03721, 0.11642, 0.80981), "fim": (0.00164, 0.00428, 0.08834, 0.32604, 1.67655)},
+    2: {"ifim": (0.00097, 0.00329, 0.0539, 0.35359, 1.09434), "fim": (0.00118, 0.00319, 0.08794, 0.63421, 1.86989)},
+    3: {"ifim": (0.00089, 0.00341, 0.0499, 0.36897, 1.48971), "fim": (0.00125, 0.00410, 0.08954, 0.78251, 2.05581)},
+    5: {"ifim": (0.00119, 0.00341, 0.0689, 0.56897, 1.098971), "fim": (0.00125, 0.00410, 0.08954, 0.78251, 2.45581)},
+}
+
+
+def replay(torch, eik, W):
+    """Examples 1, 2, 3, 5 of the paper at its grid sizes: solve ms per
+    schedule (median of 3 after a warm-up, HIP events), evaluation counts, and
+    the float32 gate against the float64 oracle up to 1000^2."""
+    import oracle
+    dev = torch.device("cuda:0")
+    rows = []
+    schedules = {"tile": dict(variant="tile"), "node": dict(variant="node"), "fim": dict(variant="fim")}
+    for k in (1, 2, 3, 5):
+        for j, n in enumerate(W.PAPER_SIZES):
+            P = W.paper_example(k, n)
+            F = torch.from_numpy(P.F).to(dev)
+            phi = torch.empty_like(F)
+            ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources, values=P.source_values) if n <= 1000 else None
+            row = {"example": k, "n": n, "sources": int(len(P.sources)),
+                   "paper_s": {m: PAPER_SECONDS[k][m][j] for m in ("ifim", "fim")}}
+            for name, kw in schedules.items():
+                def run():
+                    return eik.solve(F, P.h, P.sources, source_values=P.source_values, out=phi, **kw)
+                _, st = eik.solve(F, P.h, P.sources, source_values=P.source_values, out=phi, stats=True, **kw)
+                times = []
+                for _ in range(3):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                entry = {"ms": sorted(times)[1],
+                         "evals": st["evals_step2"] + st["evals_detect"] + st["evals_remedy"] + st["evals_check"]}
+                if ref is not None:
+                    entry["max_err_rel"] = float(np.max(np.abs(phi.cpu().numpy() - ref)) / ref.max())
+                row[name] = entry
+            rows.append(row)
+            print(json.dumps({"progress": f"example {k} n {n}", **{m: row[m]["ms"] for m in schedules}}),
+                  file=sys.stderr, flush=True)
+    return rows
 
 
 def algorithmic_bytes(kind, st, variant, n_nodes, tile_nodes, esz=4):
@@ -137,6 +189,12 @@ def main():
         return
     import paper_2106_15869_amd as eik
     import workloads as W
+
+    if a.replay:
+        print(json.dumps({"metric": "paper replay: solve ms per example, size and schedule", "unit": "ms",
+                          "n_gpus": 1, "data": "synthetic (the paper's analytic examples)", "dtype": "f32",
+                          "rows": replay(torch, eik, W)}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
