@@ -49,6 +49,9 @@ def parse():
                     help="only run one device-to-device copy of MIB MiB (for scaling HBM counters)")
     ap.add_argument("--replay", action="store_true",
                     help="instead: the paper's Examples 1, 2, 3, 5 at 200^2 .. 4000^2 with every schedule")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="instead: COUNT uneven 2D lognormal grids (sides 128..2048) solved forward + adjoint "
+                         "in one captured graph with a tuned tile")
     return ap.parse_args()
 
 
@@ -60,6 +63,100 @@ PAPER_SECONDS = {
     3: {"ifim": (0.00089, 0.00341, 0.0499, 0.36897, 1.48971), "fim": (0.00125, 0.00410, 0.08954, 0.78251, 2.05581)},
     5: {"ifim": (0.00119, 0.00341, 0.0689, 0.56897, 1.098971), "fim": (0.00125, 0.00410, 0.08954, 0.78251, 2.45581)},
 }
+
+
+def batch_bench(torch, eik, W, count, steps):
+    """Many independent 2D grids (the batch recipe): tile shape from eik_tune on
+    the largest grid; one eager forward + adjoint (stats, loop lengths); then
+    forward + adjoint enqueued asynchronously with a fixed launch budget,
+    captured in one graph and replayed; parity of a seeded sample of 8 grids
+    against the float64 oracle."""
+    import oracle
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    Ps = W.batch_2d(count)
+    gen_s = time.perf_counter() - t0
+    print(f"[batch] generated {count} grids in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    shapes = [P.F.shape for P in Ps]
+    hs = [P.h for P in Ps]
+    srcs = [P.sources for P in Ps]
+    F = torch.from_numpy(np.concatenate([P.F.ravel() for P in Ps])).to(dev)
+    g = np.concatenate([np.where(np.isin(np.arange(P.F.size), P.receivers), 1.0, 0.0) for P in Ps])
+    G = torch.from_numpy(g.astype(np.float32)).to(dev)
+    n = F.numel()
+    big = max(Ps, key=lambda P: P.F.size)
+    tuned = eik.tune(torch.from_numpy(big.F).to(dev), big.h, big.sources)
+    kw = dict(tile=tuned["tile"], inner_iters=tuned["inner_iters"])
+    print(f"[batch] tuned: {kw}", file=sys.stderr, flush=True)
+    phi, st = eik.solve_batch(F, shapes, hs, srcs, stats=True, **kw)
+    d, sta = eik.adjoint_batch(F, phi, shapes, hs, srcs, G, stats=True)
+    torch.cuda.synchronize()
+    # eager timing
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        eik.solve_batch(F, shapes, hs, srcs, out=phi, **kw)
+        eik.adjoint_batch(F, phi, shapes, hs, srcs, G, out=d)
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
+    # fixed launch budgets from the eager run, then one captured graph
+    budget = int(1.25 * max(st["step2_iters"], st["step3_iters"])) + 32
+    abudget = int(1.25 * sta["step3_iters"]) + 32
+    opt = eik.make_options(eik.EIK_FLOAT32, "tile", tile=kw["tile"])
+    ws = torch.empty(eik.eik_batch_workspace_size(shapes, hs, srcs, opt), dtype=torch.uint8, device=dev)
+    wa = torch.empty(eik.eik_adjoint_batch_workspace_size(shapes, hs, srcs, opt), dtype=torch.uint8, device=dev)
+    phi_g, d_g = torch.empty_like(F), torch.empty_like(F)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def enqueue():
+        eik.solve_batch(F, shapes, hs, srcs, out=phi_g, workspace=ws, max_iters=budget, async_=True, stream=s, **kw)
+        eik.adjoint_batch(F, phi_g, shapes, hs, srcs, G, out=d_g, workspace=wa, max_iters=abudget, async_=True,
+                          stream=s)
+    with torch.cuda.stream(s):
+        enqueue()  # warm-up of the async path on the capture stream
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            enqueue()
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    print(f"[batch] eager {eager_ms:.1f} ms, graph {graph_ms:.1f} ms", file=sys.stderr, flush=True)
+    # parity on a sample
+    r = np.random.default_rng(W.BASE_SEED)
+    sample = sorted(int(i) for i in r.choice(len(Ps), size=min(8, len(Ps)), replace=False))
+    offs = np.concatenate([[0], np.cumsum([P.F.size for P in Ps])])
+    phis, ds = phi_g.cpu().numpy(), d_g.cpu().numpy()
+    worst_phi, worst_adj = 0.0, 0.0
+    for i in sample:
+        P = Ps[i]
+        got = phis[offs[i]:offs[i + 1]].reshape(P.F.shape).astype(np.float64)
+        ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+        worst_phi = max(worst_phi, float(np.max(np.abs(got - ref)) / ref.max()))
+        gi = g[offs[i]:offs[i + 1]].reshape(P.F.shape)
+        dref = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, got, gi)
+        dg = ds[offs[i]:offs[i + 1]].reshape(P.F.shape)
+        worst_adj = max(worst_adj, float(np.linalg.norm(dg - dref) / np.linalg.norm(dref)))
+    return {"metric": "batched forward + adjoint, node-updates/s", "value": n / (graph_ms / 1e3),
+            "unit": "node-updates/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{count} 2D lognormal grids, sides U{{128..2048}}, 1-8 sources each, "
+                                   "16 receivers on the last row (L = sum of phi there)", "nodes": n,
+                       "tile": list(kw["tile"]), "inner_iters": kw["inner_iters"]},
+            "graph_ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
+            "launch_budget": {"forward": budget, "adjoint": abudget},
+            "tune": tuned, "stats_forward": st, "stats_adjoint": sta,
+            "parity_sample": {"instances": sample, "max_err_rel_phi": worst_phi, "adjoint_rel_l2": worst_adj},
+            "host_generation_s": gen_s}
 
 
 def replay(torch, eik, W):
@@ -190,6 +287,9 @@ def main():
     import paper_2106_15869_amd as eik
     import workloads as W
 
+    if a.batch:
+        print(json.dumps(batch_bench(torch, eik, W, a.batch, a.steps)), flush=True)
+        return
     if a.replay:
         print(json.dumps({"metric": "paper replay: solve ms per example, size and schedule", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic (the paper's analytic examples)", "dtype": "f32",

@@ -67,3 +67,31 @@ def test_layered_192_forward_and_adjoint():
     # Euler identity on the GPU result: sum F dL/dF = -sum_r phi_r
     L = float(got.flat[P.receivers].sum())
     assert float((P.F.astype(np.float64) * d).sum()) == pytest.approx(-L, rel=1e-4)
+
+
+def test_batch_256_sampled():
+    """The batch recipe at full size (256 grids, sides 128..2048): forward and
+    adjoint of the whole batch, eight seeded grids checked against the
+    oracle (float32 gate for phi; adjoint on the GPU's phi, relative L2)."""
+    Ps = W.batch_2d(256)
+    print(f"[case] batch 256, {sum(P.F.size for P in Ps)} nodes", flush=True)
+    shapes = [P.F.shape for P in Ps]
+    F = torch.from_numpy(np.concatenate([P.F.ravel() for P in Ps])).to(DEV)
+    g = np.concatenate([np.where(np.isin(np.arange(P.F.size), P.receivers), 1.0, 0.0) for P in Ps])
+    phi = eik.solve_batch(F, shapes, [P.h for P in Ps], [P.sources for P in Ps])
+    d = eik.adjoint_batch(F, phi, shapes, [P.h for P in Ps], [P.sources for P in Ps],
+                          torch.from_numpy(g.astype(np.float32)).to(DEV))
+    phis, ds = phi.cpu().numpy(), d.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([P.F.size for P in Ps])])
+    r = np.random.default_rng(W.BASE_SEED)
+    for i in sorted(int(v) for v in r.choice(len(Ps), size=8, replace=False)):
+        P = Ps[i]
+        got = phis[offs[i]:offs[i + 1]].reshape(P.F.shape).astype(np.float64)
+        ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+        err = np.max(np.abs(got - ref)) / ref.max()
+        print(f"[err] instance {i} {P.F.shape}: {err:.2e}", flush=True)
+        assert err <= 1e-5
+        gi = g[offs[i]:offs[i + 1]].reshape(P.F.shape)
+        dref = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, got, gi)
+        dg = ds[offs[i]:offs[i + 1]].reshape(P.F.shape).astype(np.float64)
+        assert np.linalg.norm(dg - dref) <= 2e-2 * np.linalg.norm(dref)
