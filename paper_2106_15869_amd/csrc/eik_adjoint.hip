@@ -12,12 +12,17 @@
 //                (lower index on a tie), the weights c_ik = w_ik / W_i, D_i.
 //   Grids of a batch are tiled back to back (see eik_tile.hpp); every kernel
 //   looks up the instance of the tile it works on.
-//   k_adj_tile   tile worklist: each workgroup stages lambda and the stencil
-//                data of a tile plus halo in LDS and iterates
+//   k_adj_tile   tile work queues (eik_sched.hpp): a persistent workgroup
+//                stages lambda and the stencil data of a tile plus halo in
+//                LDS and recomputes
 //                lambda_j = g_j + sum_{i : j upwind of i} c_{i,axis} lambda_i
-//                until nothing in the tile changes; a change on a face
-//                schedules the tile across it.  The system is triangular, so
-//                the iteration ends at its unique solution whatever the order.
+//                over an LDS list: a node whose lambda changes lists the
+//                nodes upwind of it (they pull from it); across a tile face it
+//                marks that face dirty in the neighbour tile and queues it.
+//                Tiles are taken in decreasing arrival time (order keys of
+//                -phi), the direction in which lambda flows.  The system is
+//                triangular, so the iteration ends at its unique solution
+//                whatever the order.
 //   k_adj_final  dense: dL/dF = D lambda (0 at sources and unreached nodes).
 #include <utility>
 #include <vector>
@@ -26,30 +31,24 @@
 #include "eik_host.hpp"
 #include "eik_seglist.hpp"
 #include "eik_batch.hpp"
+#include "eik_sched.hpp"
 #include "eik_tile.hpp"
 
 namespace eik {
 
 namespace {
 
-constexpr int GA = 1024;          // workgroups (list segments) per tile launch
 constexpr uint8_t kSrc = 0x80u;   // stencil byte: node is a source
 // stencil byte bits: axis k present -> bit 2k; upwind on the + side -> bit 2k+1
 // (axis 0 = x, 1 = y, 2 = z)
 
 template <typename T>
-struct AdjArgs {
-    const T* F;
+struct AdjIter : Sched {
     const T* phi;
     const T* g;      // dL/dphi
     T* lam;
-    uint8_t* up;     // stencil bytes
-    T* coef;         // 3 per node (x, y, z)
-    T* D;
-    uint32_t* tstamp;
-    SegList cur, next;
-    Ctl* ctl;
-    int tag_slot;
+    const uint8_t* up;  // stencil bytes
+    const T* coef;      // 3 per node (x, y, z)
 };
 
 // ---------------------------------------------------------------------------
@@ -143,73 +142,95 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(int n, const T* __restrict
 }
 
 // ---------------------------------------------------------------------------
-template <int ND, int TX, int TY, int TZ>
-struct AShape {
-    static constexpr int LX = TX + 2, LY = TY + 2, LZ = ND == 3 ? TZ + 2 : 1;
-    static constexpr int NT = TX * TY * (ND == 3 ? TZ : 1);
-    static constexpr int NL = LX * LY * LZ;
-    static constexpr int NPT = (NT + kBlock - 1) / kBlock;
-};
-
-__device__ __forceinline__ bool claim_t(uint32_t* ts, int t, uint32_t tag) {
-    if (__hip_atomic_load(ts + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tag) return false;
-    return atomicMax(ts + t, tag) < tag;
-}
-
-// Initial list: tiles holding a nonzero dL/dphi.
+// Initial list: tiles holding a nonzero dL/dphi (all nodes to recompute),
+// keyed by the largest arrival time among those nodes.
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_seed(AdjArgs<T> a, BatchGeom<T> bg) {
-    using S = AShape<ND, TX, TY, TZ>;
-    __shared__ int s_cnt;
-    SegAppender app{&s_cnt};
-    app.init();
-    __syncthreads();
-    int lo, hi;
-    seg_slice(bg.ntiles, GA, lo, hi);
-    for (int t = lo; t < hi; ++t) {
+__global__ __launch_bounds__(kBlock) void k_adj_seed(AdjIter<T> a, BatchGeom<T> bg) {
+    using S = Shape<ND, TX, TY, TZ>;
+    __shared__ uint32_t s_key;
+    for (int t = blockIdx.x; t < bg.ntiles; t += gridDim.x) {
         const Inst<T> g = inst_of(bg, t);
         const int lt = t - g.tile_base;
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
+        if (threadIdx.x == 0) s_key = kNoKey;
+        __syncthreads();
         bool nz = false;
         for (int q = threadIdx.x; q < S::NT; q += kBlock) {
             const int x = tx * TX + q % TX, y = ty * TY + (q / TX) % TY;
             const int z = ND == 3 ? tz * TZ + q / (TX * TY) : 0;
-            if (x < g.nx && y < g.ny && z < g.nz) nz |= a.g[g.node_base + (z * g.ny + y) * g.nx + x] != T(0);
+            if (x < g.nx && y < g.ny && z < g.nz) {
+                const int i = g.node_base + (z * g.ny + y) * g.nx + x;
+                if (a.g[i] != T(0)) {
+                    nz = true;
+                    atomicMin(&s_key, order_key(-a.phi[i]));
+                }
+            }
         }
-        if (__syncthreads_or(nz) && threadIdx.x == 0 && claim_t(a.tstamp, t, 1u)) app.push_one(a.next, t);
+        if (__syncthreads_or(nz) && threadIdx.x == 0) {
+            a.mask_next[t] = kAllFaces;
+            if (a.ordered) a.key_next[t] = s_key;
+            push_keyed(a, t, 1u, s_key);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    app.publish(a.next);
 }
 
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, BatchGeom<T> bg, int inner) {
-    using S = AShape<ND, TX, TY, TZ>;
+__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> bg, int inner) {
+    using S = Shape<ND, TX, TY, TZ>;
     __shared__ T slam[S::NL];
     __shared__ T scoef[3 * S::NL];
     __shared__ uint8_t sup[S::NL];
-    __shared__ int s_pref[GA + 1];
-    __shared__ int s_cnt;
+    __shared__ T sg[S::NT];
+    __shared__ TileLists<S::NT> tl;
+    __shared__ int s_len[kSub];
+    __shared__ int s_slot;
     __shared__ int s_face;
-    SegAppender app{&s_cnt};
-    app.init();
-    const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
-    const uint32_t ntag = tag + 1;
-    const int n = seg_prefix<GA>(a.cur.count, s_pref);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) {
-        a.ctl->iters3 += 1;
-        a.ctl->visits3 += static_cast<unsigned long long>(n);
+    __shared__ uint32_t s_mask, s_key, s_kmin;
+    const uint32_t ntag = launch_tag(a);
+    const int n = list_open(a, s_len);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) a.ctl->iters3 += 1;
+    const TList src = a.ordered ? a.work : a.cur;
+    if (a.ordered) {
+        __syncthreads();
+        if (threadIdx.x < kSub) s_len[threadIdx.x] = a.work.count[threadIdx.x * kPad];
+        if (blockIdx.x == 0 && threadIdx.x < kSub) {
+            a.work_zero_count[threadIdx.x * kPad] = 0;
+            a.work_zero_fetch[threadIdx.x * kPad] = 0;
+        }
+        __syncthreads();
     }
-    int lo, hi;
-    seg_slice(n, GA, lo, hi);
-    const int sty = S::LX, stz = S::LX * S::LY;
-    for (int e = lo; e < hi; ++e) {
-        const int t = seg_entry<GA>(a.cur, s_pref, e);
+    const int k = blockIdx.x & (kSub - 1);
+    const int len = s_len[k];
+    constexpr int SY = S::LX, SZ = S::LX * S::LY;
+    unsigned long long visits = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int e = atomicAdd(src.fetch + k * kPad, 1);
+            const int tt = e < len ? src.data[static_cast<size_t>(k) * src.cap + e] : -1;
+            if (tt >= 0) {
+                if (a.ordered) {
+                    s_key = a.key_cur[tt];
+                    a.key_cur[tt] = kNoKey;
+                }
+                s_mask = a.mask_cur[tt];
+                a.mask_cur[tt] = 0u;
+            }
+            s_kmin = kNoKey;
+            s_face = 0;
+            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
+            s_slot = tt;
+        }
+        __syncthreads();
+        const int t = s_slot;
+        if (t < 0) break;
+        ++visits;
         const Inst<T> g = inst_of(bg, t);
         const int lt = t - g.tile_base;
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
+        // stage lambda, stencil bytes and coefficients with the halo (0 outside)
         for (int q = threadIdx.x; q < S::NL; q += kBlock) {
             const int lx = q % S::LX, ly = (q / S::LX) % S::LY, lz = q / (S::LX * S::LY);
             const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
@@ -227,117 +248,121 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjArgs<T> a, BatchGeom<T> 
                 scoef[3 * q + 0] = scoef[3 * q + 1] = scoef[3 * q + 2] = T(0);
             }
         }
-        if (threadIdx.x == 0) s_face = 0;
-        int Lr[S::NPT], Gr[S::NPT], facer[S::NPT];
-        bool ok[S::NPT];
-        T gr[S::NPT], lam0[S::NPT];
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            const int x = nn % TX, y = (nn / TX) % TY, z = ND == 3 ? nn / (TX * TY) : 0;
-            const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
-            ok[r] = nn < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
-            Gr[r] = g.node_base + (gz * g.ny + gy) * g.nx + gx;
-            Lr[r] = ((ND == 3 ? z + 1 : 0) * S::LY + (y + 1)) * S::LX + (x + 1);
-            int f = 0;
-            if (x == 0 && gx > 0) f |= 1;
-            if (x == TX - 1 && gx + 1 < g.nx) f |= 2;
-            if (y == 0 && gy > 0) f |= 4;
-            if (y == TY - 1 && gy + 1 < g.ny) f |= 8;
-            if (ND == 3) {
-                if (z == 0 && gz > 0) f |= 16;
-                if (z == TZ - 1 && gz + 1 < g.nz) f |= 32;
-            }
-            facer[r] = f;
-            gr[r] = ok[r] ? a.g[Gr[r]] : T(0);
+        for (int nn = threadIdx.x; nn < S::NT; nn += kBlock) {
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+            sg[nn] = ok ? a.g[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] : T(0);
+            tl.flag[0][nn] = 0u;
+            tl.flag[1][nn] = 0u;
+            tl.dirty[nn] = 0;
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) lam0[r] = ok[r] ? slam[Lr[r]] : T(0);
+        // initial list: every node on a first visit, else the nodes on the faces
+        // whose neighbour tile changed
+        const uint32_t m = s_mask;
+        for (int nn = threadIdx.x; nn < S::NT; nn += kBlock) {
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+            const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
+            if (ok && ((m & kAllFaces) || (E & static_cast<int>(m))))
+                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
+        }
+        __syncthreads();
         bool pending = false;
-        for (int it = 0;; ++it) {
-            T nv[S::NPT];
-            bool ch[S::NPT];
-            bool has = false;
-#pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                ch[r] = false;
-                nv[r] = T(0);
-                if (!ok[r]) continue;
-                const int L = Lr[r];
-                T v = gr[r];
-                // neighbour i on the - side of axis k pulls into j if its upwind on
+        int fm = 0;
+        uint32_t kmin = kNoKey;
+        int it = 0;
+        for (;; ++it) {
+            const int ncur = tl.cnt[it % 3];
+            if (ncur == 0) break;
+            if (it == inner) {
+                pending = true;
+                break;
+            }
+            const int cb = it & 1, nb = cb ^ 1;
+            int* ncnt = &tl.cnt[(it + 1) % 3];
+            if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+                // neighbour on the - side of axis k pulls into q if its upwind on
                 // axis k is its + side; on the + side, if its upwind is its - side
-                const int offs[6] = {-1, 1, -sty, sty, -stz, stz};
+                T v = sg[q];
+                const int offs[6] = {-1, 1, -SY, SY, -SZ, SZ};
 #pragma unroll
                 for (int d = 0; d < 2 * ND; ++d) {
-                    const int k = d >> 1;
-                    const int q = L + offs[d];
-                    const uint32_t u = sup[q];
-                    const bool present = (u & (1u << (2 * k))) && !(u & kSrc);
-                    const bool plus = (u >> (2 * k + 1)) & 1u;
-                    if (present && plus == ((d & 1) == 0)) v = v + scoef[3 * q + k] * slam[q];
+                    const int kx = d >> 1;
+                    const int p = Lq + offs[d];
+                    const uint32_t u = sup[p];
+                    const bool present = (u & (1u << (2 * kx))) && !(u & kSrc);
+                    const bool plus = (u >> (2 * kx + 1)) & 1u;
+                    if (present && plus == ((d & 1) == 0)) v = v + scoef[3 * p + kx] * slam[p];
                 }
-                nv[r] = v;
-                ch[r] = v != slam[L];
-                has |= ch[r];
-            }
-            pending = __syncthreads_or(has);
-            if (!pending || it == inner) break;
-            int fm = 0;
+                if (v != slam[Lq]) {
+                    slam[Lq] = v;
+                    tl.dirty[q] = 1;
+                    // the nodes upwind of q pull from it: list them
+                    const uint32_t u = sup[Lq];
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
-            for (int r = 0; r < S::NPT; ++r) {
-                if (!ch[r]) continue;
-                slam[Lr[r]] = nv[r];
-                // j's own upwind neighbours pull from j: schedule tiles across faces it
-                // has an upwind neighbour on
-                const uint32_t u = sup[Lr[r]];
-#pragma unroll
-                for (int d = 0; d < 2 * ND; ++d) {
-                    const int k = d >> 1;
-                    const bool present = u & (1u << (2 * k));
-                    const bool plus = (u >> (2 * k + 1)) & 1u;
-                    if ((facer[r] & (1 << d)) && present && plus == ((d & 1) == 1)) fm |= 1 << d;
+                    for (int kx = 0; kx < ND; ++kx) {
+                        if (!(u & (1u << (2 * kx))) || (u & kSrc)) continue;
+                        const int d = 2 * kx + static_cast<int>((u >> (2 * kx + 1)) & 1u);  // face toward it
+                        if (edge & (1 << d)) {
+                            if (open & (1 << d)) {
+                                fm |= 1 << d;
+                                const int G = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+                                kmin = min(kmin, order_key(-a.phi[G]));
+                            }
+                        } else {
+                            list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
+                        }
+                    }
                 }
             }
-            if (fm) atomicOr(&s_face, fm);
             __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r)
-            if (ok[r] && slam[Lr[r]] != lam0[r]) a.lam[Gr[r]] = slam[Lr[r]];
+        if (fm) atomicOr(&s_face, fm);
+        if (a.ordered && kmin != kNoKey) atomicMin(&s_kmin, kmin);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (pending && claim_t(a.tstamp, t, ntag)) app.push_one(a.next, t);
-            const int fm = s_face;
-            for (int d = 0; d < 2 * ND; ++d) {
-                if (!(fm & (1 << d))) continue;
-                int tn = t;
-                switch (d) {
-                    case 0: tn = t - 1; break;
-                    case 1: tn = t + 1; break;
-                    case 2: tn = t - g.ntx; break;
-                    case 3: tn = t + g.ntx; break;
-                    case 4: tn = t - g.ntx * g.nty; break;
-                    default: tn = t + g.ntx * g.nty; break;
+        if (threadIdx.x < 7) {
+            const int d = threadIdx.x;
+            const int fmask = s_face;
+            const uint32_t key = s_kmin;
+            if (d == 6) {
+                if (pending) {
+                    atomicOr(a.mask_next + t, kAllFaces);
+                    push_keyed(a, t, ntag, min(key, s_key));
                 }
-                if (claim_t(a.tstamp, tn, ntag)) app.push_one(a.next, tn);
+            } else if (d < 2 * ND && (fmask & (1 << d))) {
+                const int tn = neighbour_tile(g, t, d);
+                atomicOr(a.mask_next + tn, 1u << (d ^ 1));
+                push_keyed(a, tn, ntag, key);
             }
+        }
+        for (int nn = threadIdx.x; nn < S::NT; nn += kBlock) {
+            if (!tl.dirty[nn]) continue;
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            a.lam[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = slam[L];
         }
         __syncthreads();
     }
-    app.publish(a.next);
+    if (threadIdx.x == 0 && visits) stat_add(a.blkstat, SF_VISITS3, visits);
 }
-
 
 struct AdjWs {
     Ctl* ctl;
+    unsigned long long* blkstat;
     uint8_t* up;
     void* coef;
     void* D;
     void* lam;
-    uint32_t* tstamp;
-    SegList seg[2];
+    SchedWs q;
     void* table;
     int* tile_inst;
     size_t bytes;
@@ -354,18 +379,13 @@ AdjWs adj_layout(char* base, const Batch& b, size_t esz) {
         return p;
     };
     const size_t n = static_cast<size_t>(b.n);
-    const int cap = static_cast<int>(7 * ((b.ntiles + GA - 1) / GA) + 512);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.up = reinterpret_cast<uint8_t*>(take(n));
     w.coef = take(3 * esz * n);
     w.D = take(esz * n);
     w.lam = take(esz * n);
-    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(b.ntiles)));
-    for (int k = 0; k < 2; ++k) {
-        w.seg[k].cap = cap;
-        w.seg[k].count = reinterpret_cast<int*>(take(4 * static_cast<size_t>(GA)));
-        w.seg[k].data = reinterpret_cast<int*>(take(4 * static_cast<size_t>(cap) * GA));
-    }
+    w.q = sched_layout(take, b.ntiles);
     if (b.inst.size() > 1) {
         w.table = take((esz == 8 ? sizeof(Inst<double>) : sizeof(Inst<float>)) * b.inst.size());
         w.tile_inst = reinterpret_cast<int*>(take(4 * static_cast<size_t>(b.ntiles)));
@@ -378,11 +398,14 @@ template <typename T, int ND, int TX, int TY, int TZ>
 eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out, const eik_options& o, char* ws,
                    hipStream_t s, eik_stats* st) {
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
+    const bool ordered = (o.flags & EIK_FLAG_FIFO_REMEDY) == 0;
     AdjWs w = adj_layout(ws, b, sizeof(T));
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * b.n + 64;
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (TX + TY + TZ);
     const int dense = static_cast<int>(std::min<int64_t>((b.n + kBlock - 1) / kBlock, 1 << 20));
     const int tiles = static_cast<int>(std::min<int64_t>(b.ntiles, 1 << 16));
+    const int split_blocks = static_cast<int>(std::min<int64_t>((b.ntiles + kBlock - 1) / kBlock, 1024));
+    const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks;
     int64_t launched = 0;
     Profiler prof;
     prof.start((o.flags & EIK_FLAG_PROFILE) != 0, s);
@@ -390,11 +413,14 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     BatchGeom<T> G;
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return upload_batch_geom<T>(b, w.table, w.tile_inst, s, G, launched); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return sched_clear(w.q, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
         hipLaunchKernelGGL((k_adj_prep<T, ND, TX, TY, TZ>), dim3(tiles), dim3(kBlock), 0, s, G, F, phi, w.up,
                            static_cast<T*>(w.coef), static_cast<T*>(w.D), static_cast<T*>(w.lam), g);
         return hipGetLastError();
     }));
+    launched += 7;
     for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> sb{};
         sb.count = static_cast<int>(std::min<size_t>(kMaxSrcBatch, b.src.size() - q));
@@ -406,38 +432,49 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
         }));
         ++launched;
     }
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
-                  [&] { return launch_zero_words(w.tstamp, 4 * static_cast<size_t>(b.ntiles), s); }));
-    AdjArgs<T> a{};
-    a.F = F;
-    a.phi = phi;
-    a.g = g;
-    a.lam = static_cast<T*>(w.lam);
-    a.up = w.up;
-    a.coef = static_cast<T*>(w.coef);
-    a.D = static_cast<T*>(w.D);
-    a.tstamp = w.tstamp;
-    a.ctl = w.ctl;
-    a.next = w.seg[0];
-    // seeding claims with tag 1; the tag chain starts at tag[0] = 1 -> claims 2, ...
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        hipLaunchKernelGGL((k_adj_seed<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, a, G);
-        return hipGetLastError();
-    }));
-    launched += 4;
+    // launch t drains list t and fills list t + 1; the seeding fills list 0
+    // with tag 1 and the tag chain starts at tag[0] = 1 (claims 2, 3, ...)
+    auto iter_args = [&](int64_t t) {
+        AdjIter<T> a{};
+        sched_fill(a, w.q, t, ordered, static_cast<int>(t & 1), 1, w.ctl, w.blkstat);
+        a.phi = phi;
+        a.g = g;
+        a.lam = static_cast<T*>(w.lam);
+        a.up = w.up;
+        a.coef = static_cast<const T*>(w.coef);
+        return a;
+    };
+    {
+        AdjIter<T> a0 = iter_args(0);
+        a0.next = w.q.list_of(0);
+        a0.mask_next = w.q.tmask;  // read by launch 0
+        a0.key_next = w.q.keys;
+        a0.hist_next = w.q.hist_of(0);
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
+            hipLaunchKernelGGL((k_adj_seed<T, ND, TX, TY, TZ>), dim3(std::min<int64_t>(b.ntiles, 4096)), dim3(kBlock), 0,
+                               s, a0, G);
+            return hipGetLastError();
+        }));
+        ++launched;
+    }
     auto step = [&](int64_t t) {
-        AdjArgs<T> c = a;
-        c.cur = w.seg[t & 1];
-        c.next = w.seg[(t + 1) & 1];
-        c.tag_slot = static_cast<int>(t & 1);
+        const AdjIter<T> a = iter_args(t);
+        if (ordered) {
+            const hipError_t e = timed(prof, EIK_KERNEL_OTHER, [&] {
+                hipLaunchKernelGGL(k_tile_split, dim3(split_blocks), dim3(kBlock), 0, s, static_cast<const Sched&>(a));
+                return hipGetLastError();
+            });
+            if (e != hipSuccess) return e;
+        }
         return timed(prof, EIK_KERNEL_ADJOINT, [&] {
-            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GA), dim3(kBlock), 0, s, c, G, inner);
+            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, G, inner);
             return hipGetLastError();
         });
     };
     int64_t nl = 0;
-    eik_status rc = run_loop(step, [&](int64_t t) { return w.seg[t & 1].count; }, GA, cap, async, s, &nl);
-    launched += nl;
+    eik_status rc = run_loop(step, [&](int64_t t) { return w.q.count_of(static_cast<int>(t % 3)); }, kSub * kPad, cap,
+                             async, s, &nl);
+    launched += (ordered ? 2 : 1) * nl;
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
         hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, static_cast<int>(b.n),
                            static_cast<const T*>(w.D), static_cast<const T*>(w.lam), out);
@@ -447,11 +484,12 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     if (async) return rc;
     HostSlots& hs = host_slots();
     HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hs.blk, w.blkstat, blk_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (st) {
         *st = eik_stats{};
         st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
-        st->tile_visits_step3 = static_cast<int64_t>(hs.ctl->visits3);
+        st->tile_visits_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS3, kMaxStatBlocks));
         st->launches = launched;
         HIP_TRY(prof.collect(st));
     }

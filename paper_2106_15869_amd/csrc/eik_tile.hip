@@ -32,6 +32,7 @@
 #include "eik_host.hpp"
 #include "eik_seglist.hpp"
 #include "eik_batch.hpp"
+#include "eik_sched.hpp"
 #include "eik_tile.hpp"
 
 namespace eik {
@@ -40,85 +41,15 @@ namespace {
 
 // LDS label byte: bits 0-1 state, bit 2 passable (F > 0), bit 3 outside grid.
 constexpr uint8_t kPass = 4u, kOut = 8u;
-// Workgroups per tile launch (one list segment each).
-// Persistent workgroups per tile launch; group k = blockIdx % kSub drains
-// sub-list k of the launch's tile list.
-constexpr int GT = 2048;
-constexpr int kSub = 8;       // sub-lists per tile list
-constexpr int kPad = 32;      // ints between counters (separate cache lines)
-// Dirty-face mask bit meaning "recheck every node of the tile".
-constexpr uint32_t kAllFaces = 64u;
-// Ordered remedy: per-tile order keys (monotone 32-bit images of the
-// smallest value that made the tile pending), a histogram of them over kBins
-// bins (the top key bits: sign, exponent and the leading mantissa bits), and
-// the number of lowest-key tiles a launch processes at least.
-constexpr int kBins = 8192;
-constexpr int kBinShift = 32 - 13;  // kBins = 2^13
-constexpr int kOrderMin = 1024;
-constexpr uint32_t kNoKey = 0xffffffffu;
-
-
-// A tile list: kSub sub-lists of `cap` tile ids.  count[k * kPad] is the
-// length of sub-list k (appended with atomicAdd by producers), fetch[k * kPad]
-// the next entry a consumer of sub-list k takes (atomicAdd by consumers).
-struct TList {
-    int* data;
-    int* count;
-    int* fetch;
-    int cap;
-};
 
 template <typename T>
-struct TileIter {
+struct TileIter : Sched {
     const T* F;
     T* phi;
     uint8_t* lab;
-    uint32_t* tstamp;
-    // Per tile dirty faces (bit d) or kAllFaces, double-buffered by launch
-    // parity: a launch reads and clears `mask_cur` of the tiles it visits and
-    // sets bits only in `mask_next`, which the next launch reads.  A bit set
-    // during a launch is therefore never consumed by a visit that may have
-    // staged the neighbour's values before the change that set it.
-    uint32_t* mask_cur;
-    uint32_t* mask_next;
-    // ordered remedy (the default; EIK_FLAG_FIFO_REMEDY turns it off): keys by
-    // launch parity, histograms rotating like the list counters
-    uint32_t* key_cur;
-    uint32_t* key_next;
-    unsigned* hist_cur;
-    unsigned* hist_next;
-    unsigned* hist_zero;
-    int ordered;
-    TList work;              // ordered: the tiles of this launch, split off by k_tile_split
-    int* work_zero_count;    // counters of the other work list: cleared by the remedy launch
-    int* work_zero_fetch;
-    TList cur;
-    TList next;
-    int* zero_count;   // counters of the list two launches ahead: cleared by this launch
-    int* zero_fetch;
-    Ctl* ctl;
-    unsigned long long* blkstat;  // [kStatFields][kMaxStatBlocks], column blockIdx % kMaxStatBlocks
-    int tag_slot;
-    int phase;  // 0 update step, 1 remedy loop
-    int first;  // first launch of the remedy loop
 };
 
-__device__ __forceinline__ bool claim_tile(uint32_t* tstamp, int t, uint32_t tag) {
-    return atomicMax(tstamp + t, tag) < tag;
-}
 
-
-template <int ND, int TX, int TY, int TZ>
-struct Shape {
-    static constexpr int LX = TX + 2;
-    static constexpr int LY = TY + 2;
-    static constexpr int LZ = ND == 3 ? TZ + 2 : 1;
-    static constexpr int NT = TX * TY * (ND == 3 ? TZ : 1);
-    static constexpr int NL = LX * LY * LZ;
-    static constexpr int NPT = (NT + kBlock - 1) / kBlock;
-    static constexpr int SY = LX;
-    static constexpr int SZ = LX * LY;
-};
 
 // Per-node value kept in LDS for the local solve: H = h / F (+inf on a
 // barrier), or with per-axis spacing the speed F itself (0 on a barrier).
@@ -239,208 +170,7 @@ __device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& 
 }
 
 
-template <int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ int lds_offset(int d) {
-    using S = Shape<ND, TX, TY, TZ>;
-    switch (d) {
-        case 0: return -1;
-        case 1: return 1;
-        case 2: return -S::SY;
-        case 3: return S::SY;
-        case 4: return -S::SZ;
-        default: return S::SZ;
-    }
-}
 
-template <typename T>
-__device__ __forceinline__ int neighbour_tile(const Inst<T>& g, int t, int d) {
-    switch (d) {
-        case 0: return t - 1;
-        case 1: return t + 1;
-        case 2: return t - g.ntx;
-        case 3: return t + g.ntx;
-        case 4: return t - g.ntx * g.nty;
-        default: return t + g.ntx * g.nty;
-    }
-}
-
-// Tag chain: launch with slot p reads tag[p] and stores tag[p] + 1 into
-// tag[p ^ 1]; tiles it schedules are claimed with tag[p] + 1.
-template <typename T>
-__device__ __forceinline__ uint32_t launch_tag(const TileIter<T>& a) {
-    const uint32_t tag = static_cast<uint32_t>(a.ctl->tag[a.tag_slot]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->tag[a.tag_slot ^ 1] = static_cast<int>(tag + 1);
-    return tag + 1;
-}
-
-template <typename T>
-__device__ __forceinline__ void launch_stats(const TileIter<T>& a, int n) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long un = static_cast<unsigned long long>(n);
-        if (n > 0) {
-            if (a.phase == 0) {
-                a.ctl->iters2 += 1;
-                if (un > a.ctl->max_active) a.ctl->max_active = un;
-            } else {
-                a.ctl->iters3 += 1;
-            }
-        }
-        if (a.first) a.ctl->remedy_init = un;
-    }
-}
-
-// Claim tile t for the next list and append it to sub-list t % kSub.
-__device__ __forceinline__ bool push_tile(const TList& out, uint32_t* tstamp, int t, uint32_t tag) {
-    if (!claim_tile(tstamp, t, tag)) return false;
-    const int k = t & (kSub - 1);
-    const int pos = atomicAdd(out.count + k * kPad, 1);
-    out.data[static_cast<size_t>(k) * out.cap + pos] = t;
-    return true;
-}
-
-// Order key of a value: unsigned integers compare like the (float) values.
-template <typename T>
-__device__ __forceinline__ uint32_t order_key(T v) {
-    const uint32_t b = __float_as_uint(static_cast<float>(v));
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ int key_bin(uint32_t key) { return static_cast<int>(key >> kBinShift); }
-
-// push_tile for the remedy: in ordered mode also lower the tile's key and
-// count the claim in the next list's histogram.
-template <typename T>
-__device__ __forceinline__ void push_keyed(const TileIter<T>& a, int t, uint32_t tag, uint32_t key) {
-    if (a.ordered) atomicMin(a.key_next + t, key);
-    if (push_tile(a.next, a.tstamp, t, tag) && a.ordered) atomicAdd(a.hist_next + key_bin(key), 1u);
-}
-
-// Ordered remedy: the largest histogram bin whose tiles this launch
-// processes -- the first bin where the running count reaches
-// min(list length, kOrderMin).  Block-wide; block 0 also clears the
-// histogram of the list two launches ahead.
-template <typename T>
-__device__ __forceinline__ int order_threshold(const TileIter<T>& a, int n, int* s_thr) {
-    constexpr int PER = kBins / kBlock;
-    __shared__ int s_wave[kBlock / 64];
-    if (blockIdx.x == 0)
-        for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_zero[j] = 0u;
-    const unsigned* h = a.hist_cur + threadIdx.x * PER;
-    int sum = 0;
-    for (int j = 0; j < PER; ++j) sum += static_cast<int>(h[j]);
-    const int incl = wave_incl_scan(sum);
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 63) s_wave[w] = incl;
-    if (threadIdx.x == 0) *s_thr = kBins - 1;
-    __syncthreads();
-    int run = incl - sum;
-    for (int q = 0; q < w; ++q) run += s_wave[q];
-    const int need = min(n, kOrderMin);
-    if (run < need && run + sum >= need) {  // exactly one thread holds the crossing bin
-        for (int j = 0; j < PER; ++j) {
-            run += static_cast<int>(h[j]);
-            if (run >= need) {
-                *s_thr = threadIdx.x * PER + j;
-                break;
-            }
-        }
-    }
-    __syncthreads();
-    return *s_thr;
-}
-
-// Clear the counters of the list two launches ahead (nobody reads or writes
-// them during this launch) and return the total length of the current list.
-template <typename T>
-__device__ __forceinline__ int list_open(const TileIter<T>& a, int* s_len) {
-    if (blockIdx.x == 0 && threadIdx.x < kSub) {
-        a.zero_count[threadIdx.x * kPad] = 0;
-        a.zero_fetch[threadIdx.x * kPad] = 0;
-    }
-    if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
-    __syncthreads();
-    int n = 0;
-#pragma unroll
-    for (int k = 0; k < kSub; ++k) n += s_len[k];
-    return n;
-}
-
-// Next entry of sub-list k for this workgroup (-1 when drained).  Lane 0
-// fetches; the value is broadcast through LDS.
-__device__ __forceinline__ int list_fetch(const TList& L, int k, int len, int* s_slot) {
-    if (threadIdx.x == 0) {
-        const int e = atomicAdd(L.fetch + k * kPad, 1);
-        *s_slot = e < len ? L.data[static_cast<size_t>(k) * L.cap + e] : -1;
-    }
-    __syncthreads();
-    const int t = *s_slot;
-    __syncthreads();
-    return t;
-}
-
-__device__ __forceinline__ void stat_add(unsigned long long* blkstat, int field, unsigned long long v) {
-    if (v) atomicAdd(blkstat + field * kMaxStatBlocks + (blockIdx.x & (kMaxStatBlocks - 1)), v);
-}
-
-// ---------------------------------------------------------------------------
-// In-tile work lists
-// ---------------------------------------------------------------------------
-// Nodes of a tile are numbered n = (z * TY + y) * TX + x.  The inner
-// iterations of a visit work on an LDS list of node ids instead of sweeping
-// all nodes: iteration it drains list it & 1 (length cnt[it % 3]) and appends
-// to list (it + 1) & 1; a per-list flag array keeps entries unique.  Only as
-// many waves as the list needs evaluate the local solver.
-template <int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ void node_loc(int n, int& x, int& y, int& z, int& L) {
-    using S = Shape<ND, TX, TY, TZ>;
-    x = n % TX;
-    y = (n / TX) % TY;
-    z = ND == 3 ? n / (TX * TY) : 0;
-    L = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
-}
-
-template <int TX, int TY>
-__device__ __forceinline__ int node_step(int d) {
-    switch (d) {
-        case 0: return -1;
-        case 1: return 1;
-        case 2: return -TX;
-        case 3: return TX;
-        case 4: return -TX * TY;
-        default: return TX * TY;
-    }
-}
-
-// bit d: the node lies on the tile face in direction d
-template <int ND, int TX, int TY, int TZ>
-__device__ __forceinline__ int edge_bits(int x, int y, int z) {
-    int e = (x == 0 ? 1 : 0) | (x == TX - 1 ? 2 : 0) | (y == 0 ? 4 : 0) | (y == TY - 1 ? 8 : 0);
-    if (ND == 3) e |= (z == 0 ? 16 : 0) | (z == TZ - 1 ? 32 : 0);
-    return e;
-}
-
-// bit d: the grid continues past the tile face in direction d
-template <int ND, int TX, int TY, int TZ, typename T>
-__device__ __forceinline__ int open_bits(const Inst<T>& g, int x0, int y0, int z0) {
-    int f = (x0 > 0 ? 1 : 0) | (x0 + TX < g.nx ? 2 : 0) | (y0 > 0 ? 4 : 0) | (y0 + TY < g.ny ? 8 : 0);
-    if (ND == 3) f |= (z0 > 0 ? 16 : 0) | (z0 + TZ < g.nz ? 32 : 0);
-    return f;
-}
-
-template <int NT>
-struct TileLists {
-    uint32_t flag[2][NT];
-    uint16_t list[2][NT];
-    uint8_t dirty[NT];  // remedy: node value changed during this visit
-    int cnt[3];
-};
-
-// Append node q to the next list once (returns whether it was added).
-template <int NT>
-__device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, int q) {
-    if (atomicExch(&tl.flag[nb][q], 1u) != 0u) return false;
-    tl.list[nb][atomicAdd(ncnt, 1)] = static_cast<uint16_t>(q);
-    return true;
-}
 
 // ---------------------------------------------------------------------------
 // STEP 2 on tiles
@@ -858,39 +588,6 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
     }
 }
 
-// Ordered remedy: before each remedy launch, one lane per entry of the
-// current list sends the tile either to the work list of the launch (its key
-// is within the threshold of order_threshold) or on to the next list with its
-// key and dirty faces.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tile_split(TileIter<T> a) {
-    __shared__ int s_len[kSub];
-    __shared__ int s_thr;
-    const uint32_t ntag = launch_tag(a);
-    if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
-    __syncthreads();
-    int n = 0;
-#pragma unroll
-    for (int k = 0; k < kSub; ++k) n += s_len[k];
-    if (n == 0) return;
-    const int thr = order_threshold(a, n, &s_thr);
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
-        int k = 0, i = e;
-        while (i >= s_len[k]) i -= s_len[k++];
-        const int t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
-        const uint32_t key = a.key_cur[t];
-        if (key_bin(key) <= thr) {
-            const int w = t & (kSub - 1);
-            a.work.data[static_cast<size_t>(w) * a.work.cap + atomicAdd(a.work.count + w * kPad, 1)] = t;
-        } else {
-            a.key_cur[t] = kNoKey;
-            const uint32_t mk = a.mask_cur[t];
-            a.mask_cur[t] = 0u;
-            if (mk) atomicOr(a.mask_next + t, mk);
-            push_keyed(a, t, ntag, key);
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // STEP 1 helpers
@@ -932,29 +629,12 @@ struct TileWs {
     Ctl* ctl;
     unsigned long long* blkstat;
     uint8_t* lab;
-    uint32_t* tstamp;
-    uint32_t* tmask;    // two arrays of ntiles dirty-face masks (by launch parity)
-    int* data[2];       // two list buffers (alternating)
-    int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}, then
-                        // 3 rotating order-key histograms of kBins counts
-    uint32_t* keys;     // two arrays of ntiles order keys (by launch parity)
-    int* work[2];       // ordered remedy: work lists (by launch parity) ...
-    int* work_counters; // ... and their {count, fetch} sets
+    SchedWs q;          // lists, stamps, masks, keys, histograms, work lists
     void* table;        // instance table (batches of more than one instance)
     int* tile_inst;     // instance of every tile (idem)
-    int cap;
     size_t bytes;
-    int* count_of(int set) const { return counters + set * 2 * kSub * kPad; }
-    int* fetch_of(int set) const { return counters + set * 2 * kSub * kPad + kSub * kPad; }
-    unsigned* hist_of(int set) const {
-        return reinterpret_cast<unsigned*>(counters + 3 * 2 * kSub * kPad) + set * kBins;
-    }
 };
 
-constexpr size_t kCounterBytes = (3 * 2 * kSub * kPad + 3 * kBins) * sizeof(int);
-constexpr size_t kWorkCounterBytes = 2 * 2 * kSub * kPad * sizeof(int);
-
-// A sub-list can receive every tile (tiles are deduplicated per list).
 TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t inst_bytes) {
     TileWs w{};
     size_t off = 0;
@@ -963,17 +643,10 @@ TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t i
         off = align_up(off + b, 256);
         return p;
     };
-    w.cap = static_cast<int>(ntiles + 64);
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
-    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
-    w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
-    w.counters = reinterpret_cast<int*>(take(kCounterBytes));
-    w.keys = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
-    for (int k = 0; k < 2; ++k) w.work[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
-    w.work_counters = reinterpret_cast<int*>(take(kWorkCounterBytes));
-    for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
+    w.q = sched_layout(take, ntiles);
     if (ninst > 1) {
         w.table = take(inst_bytes * ninst);
         w.tile_inst = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
@@ -1108,18 +781,9 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_ctl_init(w.ctl, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.blkstat, blk_bytes, s); }));
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_init<T>(F, phi, w.lab, nullptr, static_cast<int>(b.n), w.ctl, s); }));
-    // tile stamps and dirty-face masks are adjacent: clear both
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
-        return launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + 2 * static_cast<size_t>(ntiles)), s);
-    }));
-    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
-    launched += 5;
+    HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return sched_clear(w.q, s); }));
+    launched += 7;
     const bool ordered = (o.flags & EIK_FLAG_FIFO_REMEDY) == 0;
-    if (ordered) {
-        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_fill_words(w.keys, 2 * static_cast<size_t>(ntiles), kNoKey, s); }));
-        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.work_counters, kWorkCounterBytes, s); }));
-        launched += 2;
-    }
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> sb{};
@@ -1134,20 +798,13 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     for (auto& sb : batches)
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_seed<T>(phi, w.lab, sb, s); }));
     launched += static_cast<int64_t>(batches.size());
-    auto list_of = [&](int64_t t) {
-        TList L;
-        L.data = w.data[t & 1];
-        L.count = w.count_of(static_cast<int>(t % 3));
-        L.fetch = w.fetch_of(static_cast<int>(t % 3));
-        L.cap = w.cap;
-        return L;
-    };
+    auto list_of = [&](int64_t t) { return w.q.list_of(t); };
     if (batches.size() <= 8) {
         // tiles next to the sources
         for (auto& sb : batches)
             HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
                 hipLaunchKernelGGL(k_seed_tiles<T>, dim3(1), dim3(kMaxSrcBatch), 0, s, geom, b.nd, c.tx, c.ty, c.tz,
-                                   sb, w.tstamp, list_of(0));
+                                   sb, w.q.tstamp, list_of(0));
                 return hipGetLastError();
             }));
         launched += static_cast<int64_t>(batches.size());
@@ -1155,7 +812,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         // many sources: start from every tile; tiles with nothing to do drop out
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
             hipLaunchKernelGGL(k_seed_all_tiles, dim3(std::min((ntiles + kBlock - 1) / kBlock, 1024)), dim3(kBlock),
-                               0, s, ntiles, w.tstamp, list_of(0));
+                               0, s, ntiles, w.q.tstamp, list_of(0));
             return hipGetLastError();
         }));
         launched += 1;
@@ -1167,41 +824,13 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     // and three counter sets (the set of list t + 2 is cleared by launch t)
     auto iter_args = [&](int64_t t, int phase) {
         TileIter<T> a{};
+        sched_fill(a, w.q, t, ordered && phase == 1, static_cast<int>((gl + t) & 1), phase, w.ctl, w.blkstat);
         a.F = F;
         a.phi = phi;
         a.lab = w.lab;
-        a.tstamp = w.tstamp;
-        a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * ntiles;
-        a.mask_next = w.tmask + static_cast<size_t>((t + 1) & 1) * ntiles;
-        a.key_cur = w.keys + static_cast<size_t>(t & 1) * ntiles;
-        a.key_next = w.keys + static_cast<size_t>((t + 1) & 1) * ntiles;
-        a.hist_cur = w.hist_of(static_cast<int>(t % 3));
-        a.hist_next = w.hist_of(static_cast<int>((t + 1) % 3));
-        a.hist_zero = w.hist_of(static_cast<int>((t + 2) % 3));
-        a.ordered = (ordered && phase == 1) ? 1 : 0;
-        auto work_of = [&](int64_t u) {
-            TList L;
-            L.data = w.work[u & 1];
-            L.count = w.work_counters + (u & 1) * 2 * kSub * kPad;
-            L.fetch = L.count + kSub * kPad;
-            L.cap = w.cap;
-            return L;
-        };
-        a.work = work_of(t);
-        a.work_zero_count = work_of(t + 1).count;
-        a.work_zero_fetch = work_of(t + 1).fetch;
-        a.cur = list_of(t);
-        a.next = list_of(t + 1);
-        a.zero_count = w.count_of(static_cast<int>((t + 2) % 3));
-        a.zero_fetch = w.fetch_of(static_cast<int>((t + 2) % 3));
-        a.ctl = w.ctl;
-        a.blkstat = w.blkstat;
-        a.tag_slot = static_cast<int>((gl + t) & 1);
-        a.phase = phase;
-        a.first = (phase == 1 && t == 0) ? 1 : 0;
         return a;
     };
-    auto counts = [&](int64_t t) { return w.count_of(static_cast<int>(t % 3)); };
+    auto counts = [&](int64_t t) { return w.q.count_of(static_cast<int>(t % 3)); };
 
     int64_t n2 = 0;
     eik_status rc = run_loop(
@@ -1213,12 +842,12 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // detection fills list 0 of the remedy loop
-        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.counters, kCounterBytes, s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.q.counters, kCounterBytes, s); }));
         TileIter<T> d = iter_args(0, 1);  // only `next` (list 0), its masks and the tag are used
         d.next = list_of(0);
-        d.mask_next = w.tmask;  // read by remedy launch 0
-        d.key_next = w.keys;
-        d.hist_next = w.hist_of(0);
+        d.mask_next = w.q.tmask;  // read by remedy launch 0
+        d.key_next = w.q.keys;
+        d.hist_next = w.q.hist_of(0);
         d.first = 0;
         d.tag_slot = static_cast<int>(gl & 1);
         HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, geom, eT, s); }));
@@ -1231,7 +860,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
                 const TileIter<T> a = iter_args(t, 1);
                 if (ordered) {
                     const hipError_t e = timed(prof, EIK_KERNEL_OTHER, [&] {
-                        hipLaunchKernelGGL(k_tile_split<T>, dim3(split_blocks), dim3(kBlock), 0, s, a);
+                        hipLaunchKernelGGL(k_tile_split, dim3(split_blocks), dim3(kBlock), 0, s, static_cast<const Sched&>(a));
                         return hipGetLastError();
                     });
                     if (e != hipSuccess) return e;
