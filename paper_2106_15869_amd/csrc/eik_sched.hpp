@@ -293,6 +293,26 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 // current list sends the tile either to the work list of the launch (its key
 // is within the threshold of order_threshold) or on to the next list with its
 // key and dirty faces.
+// Append tile t for the lanes with `take` to sub-list t % kSub of L, one
+// atomic per wave and sub-list (every lane of the wave calls).
+__device__ __forceinline__ void wave_push(const TList& L, int t, bool take) {
+    const int mine = take ? (t & (kSub - 1)) : -1;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) {
+        const uint64_t m = __ballot(mine == k);
+        if (m == 0) continue;
+        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(L.count + k * kPad, __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (mine == k) {
+            const uint32_t lo = static_cast<uint32_t>(m), hi = static_cast<uint32_t>(m >> 32);
+            L.data[static_cast<size_t>(k) * L.cap + base +
+                   __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))] = t;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     __shared__ int s_len[kSub];
     __shared__ int s_thr;
@@ -302,23 +322,33 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     int n = 0;
 #pragma unroll
     for (int k = 0; k < kSub; ++k) n += s_len[k];
-    if (n == 0) return;
+    // blocks past the list's end have nothing to do (block 0 always clears the
+    // histogram of the list two launches ahead)
+    if (n == 0 || (blockIdx.x > 0 && static_cast<int>(blockIdx.x) * kBlock >= n)) return;
     const int thr = order_threshold(a, n, &s_thr);
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
-        int k = 0, i = e;
-        while (i >= s_len[k]) i -= s_len[k++];
-        const int t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
-        const uint32_t key = a.key_cur[t];
-        if (key_bin(key) <= thr) {
-            const int w = t & (kSub - 1);
-            a.work.data[static_cast<size_t>(w) * a.work.cap + atomicAdd(a.work.count + w * kPad, 1)] = t;
-        } else {
+    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const int e = base + threadIdx.x;
+        int t = -1;
+        uint32_t key = kNoKey;
+        if (e < n) {
+            int k = 0, i = e;
+            while (i >= s_len[k]) i -= s_len[k++];
+            t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
+            key = a.key_cur[t];
+        }
+        const bool now = t >= 0 && key_bin(key) <= thr;
+        bool defer = t >= 0 && !now;
+        if (defer) {
             a.key_cur[t] = kNoKey;
             const uint32_t mk = a.mask_cur[t];
             a.mask_cur[t] = 0u;
             if (mk) atomicOr(a.mask_next + t, mk);
-            push_keyed(a, t, ntag, key);
+            atomicMin(a.key_next + t, key);
+            defer = claim_tile(a.tstamp, t, ntag);  // claimed already: a producer queued it
+            if (defer) atomicAdd(a.hist_next + key_bin(key), 1u);
         }
+        wave_push(a.work, t, now);
+        wave_push(a.next, t, defer);
     }
 }
 
