@@ -168,7 +168,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(AdjIter<T> a, BatchGeom<T> 
         }
         if (__syncthreads_or(nz) && threadIdx.x == 0) {
             a.mask_next[t] = kAllFaces;
-            if (a.ordered) a.key_next[t] = s_key;
             push_keyed(a, t, 1u, s_key);
         }
         __syncthreads();

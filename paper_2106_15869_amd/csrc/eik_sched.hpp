@@ -59,7 +59,6 @@ struct Sched {
     uint32_t* key_next;
     unsigned* hist_cur;
     unsigned* hist_next;
-    unsigned* hist_zero;
     int ordered;
     TList work;              // ordered: the tiles of this launch, split off by k_tile_split
     int* work_zero_count;    // counters of the other work list: cleared by the consuming launch
@@ -156,22 +155,32 @@ __device__ __forceinline__ uint32_t order_key(T v) {
 }
 __device__ __forceinline__ int key_bin(uint32_t key) { return static_cast<int>(key >> kBinShift); }
 
-// push_tile for the remedy: in ordered mode also lower the tile's key and
-// count the claim in the next list's histogram.
+// push_tile with an order key: in ordered mode the tile's key in the next
+// list drops to `key` if lower, and the next list's histogram counts every
+// listed tile in the bin of its current key.  The keys of a list start at
+// kNoKey, so the push that sees kNoKey counts the tile, and a push that lowers
+// the key into a lower bin moves the count; the chain of lowering pushes is
+// ordered by atomicMin, so the histogram is exact once the launch ends.
 __device__ __forceinline__ void push_keyed(const Sched& a, int t, uint32_t tag, uint32_t key) {
-    if (a.ordered) atomicMin(a.key_next + t, key);
-    if (push_tile(a.next, a.tstamp, t, tag) && a.ordered) atomicAdd(a.hist_next + key_bin(key), 1u);
+    if (a.ordered) {
+        const uint32_t old = atomicMin(a.key_next + t, key);
+        const int nb = key_bin(key);
+        if (old == kNoKey) {
+            atomicAdd(a.hist_next + nb, 1u);
+        } else if (nb < key_bin(old)) {
+            atomicSub(a.hist_next + key_bin(old), 1u);
+            atomicAdd(a.hist_next + nb, 1u);
+        }
+    }
+    push_tile(a.next, a.tstamp, t, tag);
 }
 
 // Ordered remedy: the largest histogram bin whose tiles this launch
 // processes -- the first bin where the running count reaches
-// min(list length, kOrderMin).  Block-wide; block 0 also clears the
-// histogram of the list two launches ahead.
+// min(list length, kOrderMin).  Block-wide.
 __device__ __forceinline__ int order_threshold(const Sched& a, int n, int* s_thr) {
     constexpr int PER = kBins / kBlock;
     __shared__ int s_wave[kBlock / 64];
-    if (blockIdx.x == 0)
-        for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_zero[j] = 0u;
     const unsigned* h = a.hist_cur + threadIdx.x * PER;
     int sum = 0;
     for (int j = 0; j < PER; ++j) sum += static_cast<int>(h[j]);
@@ -293,26 +302,6 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 // current list sends the tile either to the work list of the launch (its key
 // is within the threshold of order_threshold) or on to the next list with its
 // key and dirty faces.
-// Append tile t for the lanes with `take` to sub-list t % kSub of L, one
-// atomic per wave and sub-list (every lane of the wave calls).
-__device__ __forceinline__ void wave_push(const TList& L, int t, bool take) {
-    const int mine = take ? (t & (kSub - 1)) : -1;
-#pragma unroll
-    for (int k = 0; k < kSub; ++k) {
-        const uint64_t m = __ballot(mine == k);
-        if (m == 0) continue;
-        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(L.count + k * kPad, __popcll(m));
-        base = __shfl(base, leader, 64);
-        if (mine == k) {
-            const uint32_t lo = static_cast<uint32_t>(m), hi = static_cast<uint32_t>(m >> 32);
-            L.data[static_cast<size_t>(k) * L.cap + base +
-                   __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))] = t;
-        }
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     __shared__ int s_len[kSub];
     __shared__ int s_thr;
@@ -322,10 +311,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     int n = 0;
 #pragma unroll
     for (int k = 0; k < kSub; ++k) n += s_len[k];
-    // blocks past the list's end have nothing to do (block 0 always clears the
-    // histogram of the list two launches ahead)
+    // blocks past the list's end have nothing to do; an empty list stays
+    // empty (nothing is processed that could queue tiles)
     if (n == 0 || (blockIdx.x > 0 && static_cast<int>(blockIdx.x) * kBlock >= n)) return;
     const int thr = order_threshold(a, n, &s_thr);
+    // The deferred tiles are the listed tiles with key bins above thr, and
+    // the current histogram counts the listed tiles by key bin, so the next
+    // list's histogram starts as its part above thr (the launch that adds to
+    // it runs after this one).  The active blocks share the bins.
+    const int nact = min(static_cast<int>(gridDim.x), (n + kBlock - 1) / kBlock);
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < kBins; j += nact * kBlock)
+        a.hist_next[j] = j > thr ? a.hist_cur[j] : 0u;
+    // appends are counted per sub-list in LDS and reserved with one global
+    // atomic per (list, sub-list) and block: thousands of waves hitting the
+    // same list counters would otherwise queue behind each other
+    __shared__ int s_cnt[2 * kSub];
+    __shared__ int s_base[2 * kSub];
     for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const int e = base + threadIdx.x;
         int t = -1;
@@ -337,18 +338,35 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
             key = a.key_cur[t];
         }
         const bool now = t >= 0 && key_bin(key) <= thr;
-        bool defer = t >= 0 && !now;
+        const bool defer = t >= 0 && !now;
         if (defer) {
+            // A tile appears once in the current list and the launch that
+            // queues tiles for the next list runs after this one, so the
+            // deferred tile's stamp, key and dirty faces carry over with plain
+            // stores (the stamp tells that launch the tile is queued already).
             a.key_cur[t] = kNoKey;
             const uint32_t mk = a.mask_cur[t];
             a.mask_cur[t] = 0u;
-            if (mk) atomicOr(a.mask_next + t, mk);
-            atomicMin(a.key_next + t, key);
-            defer = claim_tile(a.tstamp, t, ntag);  // claimed already: a producer queued it
-            if (defer) atomicAdd(a.hist_next + key_bin(key), 1u);
+            a.mask_next[t] = mk;
+            a.key_next[t] = key;
+            a.tstamp[t] = ntag;
         }
-        wave_push(a.work, t, now);
-        wave_push(a.next, t, defer);
+        for (int j = threadIdx.x; j < 2 * kSub; j += kBlock) s_cnt[j] = 0;
+        __syncthreads();
+        const int slot = (now ? 0 : kSub) + (t & (kSub - 1));
+        const int pos = (now || defer) ? atomicAdd(&s_cnt[slot], 1) : 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < 2 * kSub; j += kBlock) {
+            const TList& L = j < kSub ? a.work : a.next;
+            const int k = j & (kSub - 1);
+            s_base[j] = s_cnt[j] ? atomicAdd(L.count + k * kPad, s_cnt[j]) : 0;
+        }
+        __syncthreads();
+        if (now || defer) {
+            const TList& L = now ? a.work : a.next;
+            L.data[static_cast<size_t>(t & (kSub - 1)) * L.cap + s_base[slot] + pos] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -422,7 +440,6 @@ inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int 
     a.key_next = w.keys + static_cast<size_t>((t + 1) & 1) * nt;
     a.hist_cur = w.hist_of(static_cast<int>(t % 3));
     a.hist_next = w.hist_of(static_cast<int>((t + 1) % 3));
-    a.hist_zero = w.hist_of(static_cast<int>((t + 2) % 3));
     a.ordered = ordered ? 1 : 0;
     a.work = w.work_of(t);
     a.work_zero_count = w.work_of(t + 1).count;

@@ -379,7 +379,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
         if (a.ordered && flag) atomicMin(&s_key, order_key(low));
         if (__syncthreads_or(flag) && threadIdx.x == 0) {
             a.mask_next[t] = kAllFaces;  // one writer: the workgroup of tile t
-            if (a.ordered) a.key_next[t] = s_key;
             push_keyed(a, t, ntag, s_key);
         }
         __syncthreads();
