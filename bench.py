@@ -226,7 +226,8 @@ def algorithmic_bytes(kind, st, variant, n_nodes, tile_nodes, esz=4):
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current kernel sources (the hash covers
+    every source file the kernel is compiled from); else None."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -236,8 +237,11 @@ def measured_traffic(kernel):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("kernel") != kernel:
                 continue
-            src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-            if hashlib.sha256(src).hexdigest()[:16] == rec["sha256_16"]:
+            srcs = rec["sources"] if "sources" in rec else [rec["source"]]
+            h = hashlib.sha256()
+            for f in srcs:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest()[:16] == rec["sha256_16"]:
                 return rec["bytes_per_launch"]
     return None
 
