@@ -107,12 +107,22 @@ struct BatchGeom {
     int ntiles;               // over all instances
 };
 
-// Instance holding tile t (t must be uniform across the wave).
+// Instance holding tile t (t must be uniform across the wave).  A table entry
+// is read word by word into scalar registers; the two cases stay separate
+// (a shared load through a merged pointer would go through the generic
+// address space and put a memory round trip in front of every tile visit).
 template <typename T>
 __device__ __forceinline__ Inst<T> inst_of(const BatchGeom<T>& g, int t) {
     if (g.ninst == 1) return g.one;
     const int k = __builtin_amdgcn_readfirstlane(g.tile_inst[__builtin_amdgcn_readfirstlane(t)]);
-    return g.table[k];
+    constexpr int W = sizeof(Inst<T>) / 4;
+    static_assert(sizeof(Inst<T>) % 4 == 0, "Inst is read in 32-bit words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(g.table + k);
+    Inst<T> r;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (int i = 0; i < W; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return r;
 }
 
 // ---- launchers implemented in eik_nodelist.hip (T = float/double, ND = 2/3)

@@ -80,8 +80,33 @@ struct Owned {
     bool ok[NPT];
 };
 
+// Global index of in-tile node n (clamped into the grid, so that it can be
+// loaded unconditionally) and whether the node lies in the grid.
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ int owned_index(const Inst<T>& g, int x0, int y0, int z0, int n, bool& ok) {
+    using S = Shape<ND, TX, TY, TZ>;
+    const int x = n % TX, y = (n / TX) % TY, z = ND == 3 ? n / (TX * TY) : 0;
+    const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
+    ok = n < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
+    return g.node_base + (min(gz, g.nz - 1) * g.ny + min(gy, g.ny - 1)) * g.nx + min(gx, g.nx - 1);
+}
+
+// F of the nodes a lane owns (n = threadIdx.x + r * kBlock), loaded before
+// the staging so that both are in flight together.
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void load_owned_F(const Inst<T>& g, int x0, int y0, int z0, const T* F,
+                                             T (&f)[Shape<ND, TX, TY, TZ>::NPT]) {
+    using S = Shape<ND, TX, TY, TZ>;
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        bool ok;
+        f[r] = F[owned_index<T, ND, TX, TY, TZ>(g, x0, y0, z0, threadIdx.x + r * kBlock, ok)];
+    }
+}
+
 // Stage the tile and its halo: values (+inf outside) and labels (kOut outside).
-// All global loads of a lane are issued before its first LDS store.
+// Addresses are clamped into the grid, so every global load of a lane is
+// issued unconditionally, before its first LDS store (one memory round trip).
 template <typename T, int ND, int TX, int TY, int TZ>
 __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, const T* phi,
                                       const uint8_t* lab, T* sphi, uint8_t* sl) {
@@ -90,24 +115,26 @@ __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, 
     const T inf = pos_inf<T>();
     T v[NIT];
     uint8_t l[NIT];
+    bool in[NIT];
 #pragma unroll
     for (int j = 0; j < NIT; ++j) {
-        const int q = threadIdx.x + j * kBlock;
+        const int q = min(static_cast<int>(threadIdx.x) + j * kBlock, S::NL - 1);
         const int lx = q % S::LX;
         const int ly = (q / S::LX) % S::LY;
         const int lz = q / (S::LX * S::LY);
         const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
-        const bool in = q < S::NL && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-        const int G = g.node_base + (gz * g.ny + gy) * g.nx + gx;
-        v[j] = in ? phi[G] : inf;
-        l[j] = in ? lab[G] : kOut;
+        in[j] = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+        const int cx = min(max(gx, 0), g.nx - 1), cy = min(max(gy, 0), g.ny - 1), cz = min(max(gz, 0), g.nz - 1);
+        const int G = g.node_base + (cz * g.ny + cy) * g.nx + cx;
+        v[j] = phi[G];
+        l[j] = lab[G];
     }
 #pragma unroll
     for (int j = 0; j < NIT; ++j) {
         const int q = threadIdx.x + j * kBlock;
         if (q < S::NL) {
-            sphi[q] = v[j];
-            sl[q] = l[j];
+            sphi[q] = in[j] ? v[j] : inf;
+            sl[q] = in[j] ? l[j] : static_cast<uint8_t>(kOut);
         }
     }
 }
@@ -204,6 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
+        T fv[S::NPT];
+        load_owned_F<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, fv);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         bool ok[S::NPT];
         int G[S::NPT], L[S::NPT];
@@ -212,10 +241,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             const int nn = threadIdx.x + r * kBlock;
             int x, y, z;
             node_loc<ND, TX, TY, TZ>(nn, x, y, z, L[r]);
-            ok[r] = nn < S::NT && x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-            G[r] = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
+            G[r] = owned_index<T, ND, TX, TY, TZ>(g, x0, y0, z0, nn, ok[r]);
             if (nn < S::NT) {
-                sH[nn] = ok[r] ? cell_value<T, AN>(g, a.F[G[r]]) : dead_value<T, AN>();
+                sH[nn] = ok[r] ? cell_value<T, AN>(g, fv[r]) : dead_value<T, AN>();
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
             }
@@ -457,16 +485,16 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
             a.mask_cur[t] = 0u;
             s_kmin = kNoKey;
         }
+        T fv[S::NPT];
+        load_owned_F<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, fv);
         stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             const int nn = threadIdx.x + r * kBlock;
             if (nn < S::NT) {
-                int x, y, z, L;
-                node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-                const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-                const int G = g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x);
-                sH[nn] = ok ? cell_value<T, AN>(g, a.F[G]) : dead_value<T, AN>();
+                bool ok;
+                owned_index<T, ND, TX, TY, TZ>(g, x0, y0, z0, nn, ok);
+                sH[nn] = ok ? cell_value<T, AN>(g, fv[r]) : dead_value<T, AN>();
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
                 tl.dirty[nn] = 0;
