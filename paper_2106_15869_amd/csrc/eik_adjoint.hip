@@ -206,14 +206,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
     for (;;) {
         if (threadIdx.x == 0) {
             const int e = atomicAdd(src.fetch + k * kPad, 1);
-            const int tt = e < len ? src.data[static_cast<size_t>(k) * src.cap + e] : -1;
+            const size_t idx = static_cast<size_t>(k) * src.cap + e;
+            const int tt = e < len ? src.data[idx] : -1;
             if (tt >= 0) {
                 if (a.ordered) {
-                    s_key = a.key_cur[tt];
-                    a.key_cur[tt] = kNoKey;
+                    // the split moved the key and dirty faces into the work entry
+                    s_key = src.key[idx];
+                    s_mask = src.mask[idx];
+                } else {
+                    s_mask = a.mask_cur[tt];
+                    a.mask_cur[tt] = 0u;
                 }
-                s_mask = a.mask_cur[tt];
-                a.mask_cur[tt] = 0u;
             }
             s_kmin = kNoKey;
             s_face = 0;

@@ -34,11 +34,16 @@ constexpr uint32_t kNoKey = 0xffffffffu;
 // A tile list: kSub sub-lists of `cap` tile ids.  count[k * kPad] is the
 // length of sub-list k (appended with atomicAdd by producers), fetch[k * kPad]
 // the next entry a consumer of sub-list k takes (atomicAdd by consumers).
+// A work list (ordered scheduling) also holds, entry by entry, the tile's
+// order key and dirty faces, so that a consumer reads them together with the
+// tile id instead of after it.
 struct TList {
     int* data;
     int* count;
     int* fetch;
     int cap;
+    uint32_t* key = nullptr;
+    uint32_t* mask = nullptr;
 };
 
 // Scheduling state of a tile launch (shared by the forward kernels and the
@@ -339,14 +344,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
         }
         const bool now = t >= 0 && key_bin(key) <= thr;
         const bool defer = t >= 0 && !now;
+        uint32_t mk = 0u;
+        if (t >= 0) {
+            // the tile leaves the current list: its key and dirty faces go with
+            // it (into the work entry, or on to the next list)
+            a.key_cur[t] = kNoKey;
+            mk = a.mask_cur[t];
+            a.mask_cur[t] = 0u;
+        }
         if (defer) {
             // A tile appears once in the current list and the launch that
             // queues tiles for the next list runs after this one, so the
             // deferred tile's stamp, key and dirty faces carry over with plain
             // stores (the stamp tells that launch the tile is queued already).
-            a.key_cur[t] = kNoKey;
-            const uint32_t mk = a.mask_cur[t];
-            a.mask_cur[t] = 0u;
             a.mask_next[t] = mk;
             a.key_next[t] = key;
             a.tstamp[t] = ntag;
@@ -364,7 +374,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
         __syncthreads();
         if (now || defer) {
             const TList& L = now ? a.work : a.next;
-            L.data[static_cast<size_t>(t & (kSub - 1)) * L.cap + s_base[slot] + pos] = t;
+            const size_t idx = static_cast<size_t>(t & (kSub - 1)) * L.cap + s_base[slot] + pos;
+            L.data[idx] = t;
+            if (now) {
+                a.work.key[idx] = key;
+                a.work.mask[idx] = mk;
+            }
         }
         __syncthreads();
     }
@@ -383,7 +398,7 @@ struct SchedWs {
     int* counters;      // 3 rotating sets of {count[kSub*kPad], fetch[kSub*kPad]}, then
                         // 3 rotating order-key histograms of kBins counts
     uint32_t* keys;     // two arrays of ntiles order keys (by launch parity)
-    int* work[2];       // ordered: work lists (by launch parity) ...
+    int* work[2];       // ordered: work lists (by launch parity): ids, keys, masks ...
     int* work_counters; // ... and their {count, fetch} sets
     int cap;            // entries per sub-list: a sub-list can receive every tile once
     int ntiles;
@@ -407,6 +422,8 @@ struct SchedWs {
         L.count = work_counters + (t & 1) * 2 * kSub * kPad;
         L.fetch = L.count + kSub * kPad;
         L.cap = cap;
+        L.key = reinterpret_cast<uint32_t*>(L.data + static_cast<size_t>(cap) * kSub);
+        L.mask = L.key + static_cast<size_t>(cap) * kSub;
         return L;
     }
 };
@@ -421,7 +438,7 @@ SchedWs sched_layout(Take&& take, int64_t ntiles) {
     w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
     w.counters = reinterpret_cast<int*>(take(kCounterBytes));
     w.keys = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
-    for (int k = 0; k < 2; ++k) w.work[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
+    for (int k = 0; k < 2; ++k) w.work[k] = reinterpret_cast<int*>(take(12 * static_cast<size_t>(w.cap) * kSub));
     w.work_counters = reinterpret_cast<int*>(take(kWorkCounterBytes));
     for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
     return w;

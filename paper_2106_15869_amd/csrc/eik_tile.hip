@@ -461,10 +461,12 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
     for (;;) {
         if (threadIdx.x == 0) {
             const int e = atomicAdd(src.fetch + k * kPad, 1);
-            const int tt = e < len ? src.data[static_cast<size_t>(k) * src.cap + e] : -1;
-            if (tt >= 0 && a.ordered) {
-                s_key = a.key_cur[tt];
-                a.key_cur[tt] = kNoKey;
+            const size_t idx = static_cast<size_t>(k) * src.cap + e;
+            const int tt = e < len ? src.data[idx] : -1;
+            if (e < len && a.ordered) {
+                // the split moved the key and dirty faces into the work entry
+                s_key = src.key[idx];
+                s_mask = src.mask[idx];
             }
             s_slot = tt;
         }
@@ -480,9 +482,11 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         uint32_t mask_in = 0;
         if (threadIdx.x == 0) {
-            // written by the previous launch; no writer during this one
-            mask_in = a.mask_cur[t];
-            a.mask_cur[t] = 0u;
+            if (!a.ordered) {
+                // written by the previous launch; no writer during this one
+                mask_in = a.mask_cur[t];
+                a.mask_cur[t] = 0u;
+            }
             s_kmin = kNoKey;
         }
         T fv[S::NPT];
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
             s_face = 0;
             s_evals = 0;
             s_written = 0;
-            s_mask = mask_in;
+            if (!a.ordered) s_mask = mask_in;
             tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
         }
         __syncthreads();
