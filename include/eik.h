@@ -125,8 +125,11 @@ typedef struct {
 typedef struct {
     eik_dtype dtype;           /* element type of F / phi (default float32) */
     eik_variant variant;       /* default EIK_VARIANT_TILE */
-    int32_t tile[3];           /* tile extents (z, y, x); 0 = library default */
-    int32_t inner_iters;       /* tile variant: inner iterations per launch (0 = default) */
+    int32_t tile[3];           /* tile extents (z, y, x); 0 = library default
+                                  (16 x 16 in 2D, 8^3 in 3D) */
+    int32_t inner_iters;       /* tile variant: inner iterations per tile visit; 0 = default:
+                                  4 x the sum of the tile sides, except 2 x the
+                                  longest side in the 2D update step */
     int64_t max_iters;         /* cap per loop (0 = default 4 * N + 64) */
     uint32_t flags;            /* EIK_FLAG_* */
     const double* source_values; /* host, n_sources entries; NULL -> all 0 */

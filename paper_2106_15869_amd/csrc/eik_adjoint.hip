@@ -19,6 +19,9 @@
 //                over an LDS list: a node whose lambda changes lists the
 //                nodes upwind of it (they pull from it); across a tile face it
 //                marks that face dirty in the neighbour tile and queues it.
+//                lambda starts at 0 and the tiles holding a nonzero dL/dphi
+//                start queued, so every node with g_j != 0 changes on its
+//                first evaluation and passes its value on, also across a face.
 //                Tiles are taken in decreasing arrival time (order keys of
 //                -phi), the direction in which lambda flows.  The system is
 //                triangular, so the iteration ends at its unique solution
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_prep(BatchGeom<T> bg, const T* _
             coef[3 * static_cast<size_t>(i) + 1] = w[1];
             coef[3 * static_cast<size_t>(i) + 2] = w[2];
             D[i] = d;
-            lam[i] = g[i];
+            lam[i] = T(0);
         }
     }
 }
@@ -370,7 +373,7 @@ struct AdjWs {
     size_t bytes;
 };
 
-TileCfg adj_tile(int nd) { return nd == 2 ? TileCfg{32, 32, 1} : TileCfg{8, 8, 8}; }
+TileCfg adj_tile(int nd) { return nd == 2 ? TileCfg{16, 16, 1} : TileCfg{8, 8, 8}; }
 
 AdjWs adj_layout(char* base, const Batch& b, size_t esz) {
     AdjWs w{};
@@ -508,7 +511,7 @@ template <typename T>
 eik_status adjoint_solve(const Batch& b0, const T* F, const T* phi, const T* g, T* out, const eik_options& o,
                          char* ws, hipStream_t s, eik_stats* st) {
     const Batch b = with_tiles(b0, adj_tile(b0.nd));
-    if (b.nd == 2) return adj_run<T, 2, 32, 32, 1>(b, F, phi, g, out, o, ws, s, st);
+    if (b.nd == 2) return adj_run<T, 2, 16, 16, 1>(b, F, phi, g, out, o, ws, s, st);
     return adj_run<T, 3, 8, 8, 8>(b, F, phi, g, out, o, ws, s, st);
 }
 

@@ -31,9 +31,9 @@ std::map<std::tuple<int, int, int>, Choice>& tune_cache() {
 
 std::vector<Choice> candidates(int nd) {
     if (nd == 2)
-        return {{{1, 32, 32}, 0}, {{1, 32, 32}, 32}, {{1, 16, 16}, 0}, {{1, 16, 64}, 0},
+        return {{{1, 16, 16}, 0}, {{1, 16, 16}, 48}, {{1, 32, 32}, 0}, {{1, 16, 64}, 0},
                 {{1, 8, 32}, 0},  {{1, 64, 64}, 0}};
-    return {{{8, 8, 8}, 0}, {{8, 8, 8}, 32}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
+    return {{{8, 8, 8}, 0}, {{8, 8, 8}, 16}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
 }
 
 struct Events {

@@ -59,6 +59,25 @@ def test_strip_closed_form(dtype, tol):
     assert np.max(np.abs(d[0] - want)) <= tol * np.max(np.abs(want))
 
 
+# A receiver on the first or last node of a tile whose upwind neighbour lies in
+# a tile holding no receiver: its value has to cross the face (2D tiles are
+# 16 nodes wide, 3D tiles 8).  1D closed form as above.
+@pytest.mark.parametrize("shape,rec", [((1, 100), 48), ((1, 100), 64), ((1, 100), 47), ((1, 100), 95),
+                                       ((1, 1, 100), 40), ((1, 1, 100), 16), ((1, 1, 100), 71)])
+def test_strip_receiver_on_tile_face(shape, rec):
+    r = np.random.default_rng(11)
+    n = shape[-1]
+    F = np.exp(r.uniform(-1, 1, size=shape))
+    src = 3
+    P = W.Problem(f"strip_face_{len(shape)}d_{rec}", F, 0.5, np.array([src]))
+    g = np.zeros_like(F)
+    g.flat[rec] = 1.0
+    _, d = gpu_grad(P, np.float64, g)
+    want = np.zeros(n)
+    want[src + 1:rec + 1] = -0.5 / F.ravel()[src + 1:rec + 1] ** 2
+    assert np.max(np.abs(d.ravel() - want)) <= 1e-13 * np.max(np.abs(want))
+
+
 def _cases():
     return [W.lognormal_2d(96, seed=3), W.random_problem(77, 2, 60), W.random_problem(78, 3, 20),
             W.layered_3d(40, n_receivers=32), W.maze_3d(32)]
