@@ -236,31 +236,57 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         // stage lambda, stencil bytes and coefficients with the halo (0 outside)
-        for (int q = threadIdx.x; q < S::NL; q += kBlock) {
-            const int lx = q % S::LX, ly = (q / S::LX) % S::LY, lz = q / (S::LX * S::LY);
-            const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
-            const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-            if (in) {
-                const int G = g.node_base + (gz * g.ny + gy) * g.nx + gx;
-                slam[q] = a.lam[G];
-                sup[q] = a.up[G];
-                scoef[3 * q + 0] = a.coef[3 * static_cast<size_t>(G) + 0];
-                scoef[3 * q + 1] = a.coef[3 * static_cast<size_t>(G) + 1];
-                scoef[3 * q + 2] = a.coef[3 * static_cast<size_t>(G) + 2];
-            } else {
-                slam[q] = T(0);
-                sup[q] = 0;
-                scoef[3 * q + 0] = scoef[3 * q + 1] = scoef[3 * q + 2] = T(0);
+        // and dL/dphi of the tile's nodes: addresses are clamped into the grid
+        // so every global load of a lane is issued before its first LDS store
+        {
+            constexpr int NIT = (S::NL + kBlock - 1) / kBlock;
+            constexpr int NPT = (S::NT + kBlock - 1) / kBlock;
+            T vl[NIT], c0[NIT], c1[NIT], c2[NIT], vg[NPT];
+            uint8_t vu[NIT];
+            bool in[NIT], okn[NPT];
+#pragma unroll
+            for (int j = 0; j < NIT; ++j) {
+                const int q = min(static_cast<int>(threadIdx.x) + j * kBlock, S::NL - 1);
+                const int lx = q % S::LX, ly = (q / S::LX) % S::LY, lz = q / (S::LX * S::LY);
+                const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = ND == 3 ? z0 + lz - 1 : 0;
+                in[j] = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+                const int cx = min(max(gx, 0), g.nx - 1), cy = min(max(gy, 0), g.ny - 1);
+                const int cz = min(max(gz, 0), g.nz - 1);
+                const size_t G = static_cast<size_t>(g.node_base) + (cz * g.ny + cy) * g.nx + cx;
+                vl[j] = a.lam[G];
+                vu[j] = a.up[G];
+                c0[j] = a.coef[3 * G + 0];
+                c1[j] = a.coef[3 * G + 1];
+                c2[j] = a.coef[3 * G + 2];
             }
-        }
-        for (int nn = threadIdx.x; nn < S::NT; nn += kBlock) {
-            int x, y, z, L;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-            const bool ok = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
-            sg[nn] = ok ? a.g[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] : T(0);
-            tl.flag[0][nn] = 0u;
-            tl.flag[1][nn] = 0u;
-            tl.dirty[nn] = 0;
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
+                int x, y, z, L;
+                node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+                okn[r] = x0 + x < g.nx && y0 + y < g.ny && z0 + z < g.nz;
+                const int cx = min(x0 + x, g.nx - 1), cy = min(y0 + y, g.ny - 1), cz = min(z0 + z, g.nz - 1);
+                vg[r] = a.g[g.node_base + (cz * g.ny + cy) * g.nx + cx];
+            }
+#pragma unroll
+            for (int j = 0; j < NIT; ++j) {
+                const int q = threadIdx.x + j * kBlock;
+                if (q >= S::NL) continue;
+                slam[q] = in[j] ? vl[j] : T(0);
+                sup[q] = in[j] ? vu[j] : static_cast<uint8_t>(0);
+                scoef[3 * q + 0] = in[j] ? c0[j] : T(0);
+                scoef[3 * q + 1] = in[j] ? c1[j] : T(0);
+                scoef[3 * q + 2] = in[j] ? c2[j] : T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const int nn = threadIdx.x + r * kBlock;
+                if (nn >= S::NT) continue;
+                sg[nn] = okn[r] ? vg[r] : T(0);
+                tl.flag[0][nn] = 0u;
+                tl.flag[1][nn] = 0u;
+                tl.dirty[nn] = 0;
+            }
         }
         __syncthreads();
         // initial list: every node on a first visit, else the nodes on the faces
