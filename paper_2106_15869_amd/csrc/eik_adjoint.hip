@@ -467,7 +467,7 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     // with tag 1 and the tag chain starts at tag[0] = 1 (claims 2, 3, ...)
     auto iter_args = [&](int64_t t) {
         AdjIter<T> a{};
-        sched_fill(a, w.q, t, ordered, static_cast<int>(t & 1), 1, w.ctl, w.blkstat);
+        sched_fill(a, w.q, t, ordered, ND, static_cast<int>(t & 1), 1, w.ctl, w.blkstat);
         a.phi = phi;
         a.g = g;
         a.lam = static_cast<T*>(w.lam);

@@ -24,10 +24,13 @@ constexpr uint32_t kAllFaces = 64u;
 // Ordered remedy: per-tile order keys (monotone 32-bit images of the
 // smallest value that made the tile pending), a histogram of them over kBins
 // bins (the top key bits: sign, exponent and the leading mantissa bits), and
-// the number of lowest-key tiles a launch processes at least.
+// the number of lowest-key tiles a launch processes at least: in 3D 1024; a
+// 2D front is a curve and keeps fewer tiles final at a time, 512 (measured:
+// maze 256^3 and layered 192^3 best at 1024, 2D lognormal 4096^2 and the
+// paper's Example 5 at 4000^2 3-4 % faster at 512 than at 1024).
 constexpr int kBins = 8192;
 constexpr int kBinShift = 32 - 13;  // kBins = 2^13
-constexpr int kOrderMin = 1024;
+inline int order_min(int nd) { return nd == 2 ? 512 : 1024; }
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 
@@ -65,6 +68,7 @@ struct Sched {
     unsigned* hist_cur;
     unsigned* hist_next;
     int ordered;
+    int order_min;           // ordered: lowest-key tiles a launch takes at least
     TList work;              // ordered: the tiles of this launch, split off by k_tile_split
     int* work_zero_count;    // counters of the other work list: cleared by the consuming launch
     int* work_zero_fetch;
@@ -182,7 +186,7 @@ __device__ __forceinline__ void push_keyed(const Sched& a, int t, uint32_t tag, 
 
 // Ordered remedy: the largest histogram bin whose tiles this launch
 // processes -- the first bin where the running count reaches
-// min(list length, kOrderMin).  Block-wide.
+// min(list length, order_min).  Block-wide.
 __device__ __forceinline__ int order_threshold(const Sched& a, int n, int* s_thr) {
     constexpr int PER = kBins / kBlock;
     __shared__ int s_wave[kBlock / 64];
@@ -196,7 +200,7 @@ __device__ __forceinline__ int order_threshold(const Sched& a, int n, int* s_thr
     __syncthreads();
     int run = incl - sum;
     for (int q = 0; q < w; ++q) run += s_wave[q];
-    const int need = min(n, kOrderMin);
+    const int need = min(n, a.order_min);
     if (run < need && run + sum >= need) {  // exactly one thread holds the crossing bin
         for (int j = 0; j < PER; ++j) {
             run += static_cast<int>(h[j]);
@@ -447,8 +451,8 @@ SchedWs sched_layout(Take&& take, int64_t ntiles) {
 // Launch t of a loop drains list t and fills list t + 1 (the counter set of
 // list t + 2 is cleared by launch t); tag_slot is the parity in the device
 // tag chain.
-inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int tag_slot, int phase, Ctl* ctl,
-                       unsigned long long* blkstat) {
+inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int nd, int tag_slot, int phase,
+                       Ctl* ctl, unsigned long long* blkstat) {
     const size_t nt = static_cast<size_t>(w.ntiles);
     a.tstamp = w.tstamp;
     a.mask_cur = w.tmask + static_cast<size_t>(t & 1) * nt;
@@ -458,6 +462,7 @@ inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int 
     a.hist_cur = w.hist_of(static_cast<int>(t % 3));
     a.hist_next = w.hist_of(static_cast<int>((t + 1) % 3));
     a.ordered = ordered ? 1 : 0;
+    a.order_min = order_min(nd);
     a.work = w.work_of(t);
     a.work_zero_count = w.work_of(t + 1).count;
     a.work_zero_fetch = w.work_of(t + 1).fetch;

@@ -865,7 +865,8 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     // and three counter sets (the set of list t + 2 is cleared by launch t)
     auto iter_args = [&](int64_t t, int phase) {
         TileIter<T> a{};
-        sched_fill(a, w.q, t, ordered && phase == 1, static_cast<int>((gl + t) & 1), phase, w.ctl, w.blkstat);
+        sched_fill(a, w.q, t, ordered && phase == 1, b.nd, static_cast<int>((gl + t) & 1), phase, w.ctl,
+                   w.blkstat);
         a.F = F;
         a.phi = phi;
         a.lab = w.lab;
