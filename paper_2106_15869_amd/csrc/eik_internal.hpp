@@ -60,7 +60,7 @@ struct SegList {
 // Workgroups per list launch of the node-list variant (one segment each).
 constexpr int kNodeSegs = 512;
 
-// Pointers a node-list iteration needs; the driver alternates the two lists
+// Pointers a node-list iteration needs; the host loop alternates the two lists
 // by iteration parity.
 template <typename T>
 struct NodeIter {
