@@ -164,24 +164,38 @@ __device__ __forceinline__ uint32_t order_key(T v) {
 }
 __device__ __forceinline__ int key_bin(uint32_t key) { return static_cast<int>(key >> kBinShift); }
 
-// push_tile with an order key: in ordered mode the tile's key in the next
-// list drops to `key` if lower, and the next list's histogram counts every
-// listed tile in the bin of its current key.  The keys of a list start at
-// kNoKey, so the push that sees kNoKey counts the tile, and a push that lowers
-// the key into a lower bin moves the count; the chain of lowering pushes is
-// ordered by atomicMin, so the histogram is exact once the launch ends.
+// Append tile t to sub-list t % kSub of `out` (the caller has made sure it
+// is not there yet).
+__device__ __forceinline__ void append_tile(const TList& out, int t) {
+    const int k = t & (kSub - 1);
+    const int pos = atomicAdd(out.count + k * kPad, 1);
+    out.data[static_cast<size_t>(k) * out.cap + pos] = t;
+}
+
+// push_tile with an order key.  In ordered mode the tile's key in the next
+// list drops to `key` if lower, and the key array also tells membership: the
+// keys of a list start at kNoKey (a tile leaving a list has its key reset,
+// a tile carried over to the next list takes its key there), so the push
+// that sees kNoKey is the first of t into the next list and appends it.  The
+// next list's histogram counts every listed tile in the bin of its current
+// key: the first push counts it, a push that lowers the key into a lower bin
+// moves the count; the chain of lowering pushes is ordered by atomicMin, so
+// the histogram is exact once the launch ends.  Without ordering the tile
+// stamp deduplicates (push_tile).
 __device__ __forceinline__ void push_keyed(const Sched& a, int t, uint32_t tag, uint32_t key) {
-    if (a.ordered) {
-        const uint32_t old = atomicMin(a.key_next + t, key);
-        const int nb = key_bin(key);
-        if (old == kNoKey) {
-            atomicAdd(a.hist_next + nb, 1u);
-        } else if (nb < key_bin(old)) {
-            atomicSub(a.hist_next + key_bin(old), 1u);
-            atomicAdd(a.hist_next + nb, 1u);
-        }
+    if (!a.ordered) {
+        push_tile(a.next, a.tstamp, t, tag);
+        return;
     }
-    push_tile(a.next, a.tstamp, t, tag);
+    const uint32_t old = atomicMin(a.key_next + t, key);
+    const int nb = key_bin(key);
+    if (old == kNoKey) {
+        append_tile(a.next, t);
+        atomicAdd(a.hist_next + nb, 1u);
+    } else if (nb < key_bin(old)) {
+        atomicSub(a.hist_next + key_bin(old), 1u);
+        atomicAdd(a.hist_next + nb, 1u);
+    }
 }
 
 // Ordered remedy: the largest histogram bin whose tiles this launch
@@ -314,7 +328,6 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     __shared__ int s_len[kSub];
     __shared__ int s_thr;
-    const uint32_t ntag = launch_tag(a);
     if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
     __syncthreads();
     int n = 0;
@@ -359,11 +372,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
         if (defer) {
             // A tile appears once in the current list and the launch that
             // queues tiles for the next list runs after this one, so the
-            // deferred tile's stamp, key and dirty faces carry over with plain
-            // stores (the stamp tells that launch the tile is queued already).
+            // deferred tile's key and dirty faces carry over with plain stores
+            // (its key tells that launch the tile is queued already).
             a.mask_next[t] = mk;
             a.key_next[t] = key;
-            a.tstamp[t] = ntag;
         }
         for (int j = threadIdx.x; j < 2 * kSub; j += kBlock) s_cnt[j] = 0;
         __syncthreads();
