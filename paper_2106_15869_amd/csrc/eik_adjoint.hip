@@ -190,20 +190,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
     __shared__ int s_face;
     __shared__ uint32_t s_mask, s_key, s_kmin;
     const uint32_t ntag = launch_tag(a);
-    const int n = list_open(a, s_len);
+    __shared__ int s_wlen[kSub];
+    const int n = list_open(a, s_len, s_wlen);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) a.ctl->iters3 += 1;
     const TList src = a.ordered ? a.work : a.cur;
-    if (a.ordered) {
-        __syncthreads();
-        if (threadIdx.x < kSub) s_len[threadIdx.x] = a.work.count[threadIdx.x * kPad];
-        if (blockIdx.x == 0 && threadIdx.x < kSub) {
-            a.work_zero_count[threadIdx.x * kPad] = 0;
-            a.work_zero_fetch[threadIdx.x * kPad] = 0;
-        }
-        __syncthreads();
-    }
     const int k = blockIdx.x & (kSub - 1);
-    const int len = s_len[k];
+    const int len = a.ordered ? s_wlen[k] : s_len[k];
     constexpr int SY = S::LX, SZ = S::LX * S::LY;
     unsigned long long visits = 0;
     for (;;) {

@@ -230,12 +230,21 @@ __device__ __forceinline__ int order_threshold(const Sched& a, int n, int* s_thr
 
 // Clear the counters of the list two launches ahead (nobody reads or writes
 // them during this launch) and return the total length of the current list.
-__device__ __forceinline__ int list_open(const Sched& a, int* s_len) {
+// With s_wlen (a consumer of the ordered work list) the work list's lengths
+// are read in the same round and the other work list's counters cleared.
+__device__ __forceinline__ int list_open(const Sched& a, int* s_len, int* s_wlen = nullptr) {
     if (blockIdx.x == 0 && threadIdx.x < kSub) {
         a.zero_count[threadIdx.x * kPad] = 0;
         a.zero_fetch[threadIdx.x * kPad] = 0;
+        if (s_wlen && a.ordered) {
+            a.work_zero_count[threadIdx.x * kPad] = 0;
+            a.work_zero_fetch[threadIdx.x * kPad] = 0;
+        }
     }
-    if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
+    if (threadIdx.x < kSub) {
+        s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
+        if (s_wlen && a.ordered) s_wlen[threadIdx.x] = a.work.count[threadIdx.x * kPad];
+    }
     __syncthreads();
     int n = 0;
 #pragma unroll

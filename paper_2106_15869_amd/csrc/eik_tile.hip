@@ -441,22 +441,14 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::N
     __shared__ uint32_t s_key, s_kmin;
     const T inf = pos_inf<T>();
     const uint32_t ntag = launch_tag(a);
-    const int n = list_open(a, s_len);
-    launch_stats(a, n);
     // ordered mode: k_tile_split has moved this launch's tiles into the work
     // list (the rest went on to the next list)
+    __shared__ int s_wlen[kSub];
+    const int n = list_open(a, s_len, s_wlen);
+    launch_stats(a, n);
     const TList src = a.ordered ? a.work : a.cur;
-    if (a.ordered) {
-        __syncthreads();  // s_len of the current list has been read
-        if (threadIdx.x < kSub) s_len[threadIdx.x] = a.work.count[threadIdx.x * kPad];
-        if (blockIdx.x == 0 && threadIdx.x < kSub) {
-            a.work_zero_count[threadIdx.x * kPad] = 0;
-            a.work_zero_fetch[threadIdx.x * kPad] = 0;
-        }
-        __syncthreads();
-    }
     const int k = blockIdx.x & (kSub - 1);
-    const int len = s_len[k];
+    const int len = a.ordered ? s_wlen[k] : s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
     for (;;) {
         if (threadIdx.x == 0) {
