@@ -150,7 +150,7 @@ inline eik_status run_loop(StepFn step, CountsFn counts, int nseg, int64_t max_i
     HostSlots& hs = host_slots();
     if (!hs.ok) return fail(EIK_ERR_DEVICE, "pinned host buffer allocation failed");
     if (nseg > HostSlots::kWords / 2) return fail(EIK_ERR_UNSUPPORTED, "too many list segments");
-    const int64_t chunk = 16;  // even: list parity repeats
+    const int64_t chunk = 8;  // even: list parity repeats
     auto total = [&](int slot) {
         long long sum = 0;
         const int* w = hs.words + slot * (HostSlots::kWords / 2);
