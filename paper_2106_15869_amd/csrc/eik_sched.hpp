@@ -13,7 +13,6 @@
 namespace eik {
 namespace {
 
-// Workgroups per tile launch (one list segment each).
 // Persistent workgroups per tile launch; group k = blockIdx % kSub drains
 // sub-list k of the launch's tile list.
 constexpr int GT = 2048;

@@ -1,10 +1,12 @@
 // Tile-activated IFIM for gfx950.
 //
-// The grid is cut into tiles of TZ x TY x TX nodes.  A launch processes a list
-// of tiles, one workgroup (256 lanes, four wave64) per tile at a time.  Each
-// workgroup stages the tile's values and labels plus a one-cell halo in LDS,
-// then runs the node rules of Algorithm 2 for several inner iterations
-// without touching HBM, and writes back what changed.
+// The grid is cut into tiles of TZ x TY x TX nodes.  A launch drains a list
+// of tiles with persistent workgroups (256 lanes, four wave64), one tile
+// visit at a time.  A visit stages the tile's values, labels and speeds plus
+// a one-cell halo in LDS (one round of global loads), runs the node rules of
+// Algorithm 2 for several inner iterations on an LDS list of nodes without
+// touching HBM, writes back what changed and schedules the tiles that have
+// to be visited next (eik_sched.hpp: sub-list queues, stamps, order keys).
 //
 //   update step (STEP 2): FAR nodes with F > 0 next to a converged or fixed
 //     node become active; active nodes take phi~ = G_i(phi); a node whose
@@ -15,16 +17,18 @@
 //   remedy detection (STEP 3, first part): one dense pass over all tiles;
 //     a tile with any node whose phi~ < phi - eps enters the remedy list.
 //   remedy loop (STEP 3): the remedy rule of Section 3.1.2 restricted to the
-//     tile: recompute the flagged nodes, take the drops, flag the changed
-//     nodes and their in-tile neighbours for the next inner iteration, until
-//     no flagged node changes.  A tile enters with all nodes flagged (first
-//     visit) or with the nodes on the faces whose neighbour tile changed; a
-//     change on a tile face marks that face dirty in the tile across it and
-//     schedules it.
-// Within an inner iteration all phi~ are computed before any is applied (two
-// LDS phases), so a tile's iterations are synchronous; tiles of one launch see
-// each other's values only through the halo staged at the start.  Tile lists
-// are segmented per workgroup (eik_seglist.hpp).
+//     tile: recompute the listed nodes, take the drops, list the in-tile
+//     neighbours below which a dropped value now lies for the next inner
+//     iteration, until the list is empty.  A tile enters with all nodes
+//     listed (first visit) or with the nodes on the faces whose neighbour tile
+//     changed; a drop on a tile face marks that face dirty in the tile across
+//     it and schedules it with the dropped value as its order key.  By
+//     default (ordered remedy) k_tile_split hands each launch only the
+//     lowest-key tiles of the list.
+// Values are updated in place within an inner iteration (a read racing with
+// an update sees either value, both upper bounds of the solution); tiles of
+// one launch see each other's values only through the halo staged at the
+// start of a visit.
 #include <utility>
 #include <vector>
 
