@@ -425,11 +425,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
 // the next iteration when the new value lies below theirs (otherwise their
 // update cannot change: the node is not upwind of them), and a face neighbour
 // below the halo value marks that face dirty in the tile across it.
-// Occupancy matters more than a few spilled registers here: the inner
-// iterations are latency-bound, and more resident workgroups hide it (float
-// tiles of up to 512 nodes: eight waves per SIMD measured fastest).
+// Resident workgroups per CU for float tiles (the inner iterations are
+// latency-bound; occupancy against spilled registers, measured): eight for
+// tiles of one node per lane, six for two (the 8^3 tile: eight spill at
+// 64 registers, five or fewer were slower).
+template <int NPT, typename T>
+constexpr int remedy_blocks_per_cu() {
+    return sizeof(T) != 4 ? 1 : NPT == 1 ? 8 : NPT == 2 ? 6 : 1;
+}
+
 template <typename T, int ND, int TX, int TY, int TZ, bool AN>
-__global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && Shape<ND, TX, TY, TZ>::NPT <= 2) ? 8 : 1) void k_tile_remedy(
+__global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>::NPT, T>())) void k_tile_remedy(
     TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
