@@ -211,39 +211,6 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-// Append `c` (<= MAXC) items per lane to list[*cnt ...] with one atomic per
-// wave.  Must be called by every lane of the wave (c may be 0).
-template <int MAXC>
-__device__ __forceinline__ void wave_append(int* list, int* cnt, const int (&items)[MAXC], int c) {
-    int incl = wave_incl_scan(c);
-    int total = __shfl(incl, 63, 64);
-    int base = 0;
-    if (total > 0) {
-        if (lane_id() == 63) base = atomicAdd(cnt, total);
-        base = __shfl(base, 63, 64);
-    }
-    int pos = base + incl - c;
-#pragma unroll
-    for (int j = 0; j < MAXC; ++j)
-        if (j < c) list[pos + j] = items[j];
-}
-
-// Single item per lane (flag), one atomic per wave: ballot + mbcnt.
-__device__ __forceinline__ void wave_append1(int* list, int* cnt, int item, bool flag) {
-    uint64_t m = __ballot(flag);
-    if (m == 0) return;
-    int n = __popcll(m);
-    int base = 0;
-    int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    if (lane_id() == leader) base = atomicAdd(cnt, n);
-    base = __shfl(base, leader, 64);
-    if (flag) {
-        uint32_t lo = static_cast<uint32_t>(m), hi = static_cast<uint32_t>(m >> 32);
-        int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        list[base + rank] = item;
-    }
-}
-
 // Add v to this workgroup's column of a per-workgroup statistics array
 // (call from one lane only).
 __device__ __forceinline__ void blk_add(unsigned long long* blkstat, int field, int nblocks,
