@@ -128,7 +128,7 @@ typedef struct {
     int32_t tile[3];           /* tile extents (z, y, x); 0 = library default
                                   (16 x 16 in 2D, 8^3 in 3D) */
     int32_t inner_iters;       /* tile variant: inner iterations per tile visit; 0 = default:
-                                  4 x the sum of the tile sides, except 2 x the
+                                  4 x the sum of the tile sides, except the
                                   longest side in the 2D update step */
     int64_t max_iters;         /* cap per loop (0 = default 4 * N + 64) */
     uint32_t flags;            /* EIK_FLAG_* */

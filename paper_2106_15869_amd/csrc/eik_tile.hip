@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
     __shared__ uint8_t sl[S::NL];
     __shared__ T sH[S::NT];
     __shared__ TileLists<S::NT> tl;
+    __shared__ uint8_t schg[2][ND == 2 ? S::NT : 1];  // 2D: inputs changed in phase 1 (by iteration parity)
     __shared__ int s_len[kSub];
     __shared__ int s_slot;
     __shared__ int s_face;
@@ -250,6 +251,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
                 sH[nn] = ok[r] ? cell_value<T, AN>(g, fv[r]) : dead_value<T, AN>();
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
+                if (ND == 2) {
+                    schg[0][nn] = 0;
+                    schg[1][nn] = 0;
+                }
             }
         }
         if (threadIdx.x == 0) {
@@ -287,9 +292,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             if (act) tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(threadIdx.x + r * kBlock);
         }
         __syncthreads();
-        // Inner iterations on the LDS active list, values updated in place:
-        // one barrier each.  Reads racing with updates see either value, both
-        // upper bounds of the solution.
+        // Inner iterations on the LDS active list, values updated in place.
+        // Reads racing with updates see either value, both upper bounds of the
+        // solution.  Each iteration has two phases:
+        //   1. every listed node is evaluated; a value that does not move
+        //      (phi - phi~ <= eps) converges the node, a value that drops is
+        //      taken and marks the node's in-tile neighbours "inputs changed";
+        //   2. a node whose value dropped in phase 1 while none of its inputs
+        //      changed converges at once: its re-evaluation would give the
+        //      same value (the convergence test of the next iteration, known
+        //      in advance); the others are listed again.
+        // A front thus crosses one node per iteration instead of two.  In 3D
+        // phase 2 is left out (a dropped value is listed again and confirmed
+        // by its next evaluation): the extra phase and its registers cost
+        // more there than the shorter crossings save.
+        constexpr bool TWO_PHASE = ND == 2;
         bool any_active = false;
         int my_evals = 0, fm = 0;
         int it = 0;
@@ -303,6 +320,31 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             const int cb = it & 1, nb = cb ^ 1;
             int* ncnt = &tl.cnt[(it + 1) % 3];
             if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
+            // the marks of the previous iteration are no longer read
+            if (TWO_PHASE) {
+#pragma unroll
+                for (int r = 0; r < S::NPT; ++r)
+                    if (threadIdx.x + r * kBlock < S::NT) schg[nb][threadIdx.x + r * kBlock] = 0;
+            }
+            // converged node q (LDS index Lq, tile position x, y, z): CONV,
+            // its FAR neighbours become active
+            auto converge = [&](int q, int Lq, int x, int y, int z) {
+                sl[Lq] = (sl[Lq] & ~3u) | L_CONV;
+                const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
+#pragma unroll
+                for (int d = 0; d < 2 * ND; ++d) {
+                    const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                    const uint8_t lb = sl[Ln];
+                    if (edge & (1 << d)) {
+                        if ((open & (1 << d)) && (lb & 3u) == L_FAR) fm |= 1 << d;
+                    } else if (!(lb & kOut) && (lb & 3u) == L_FAR && (lb & kPass)) {
+                        if (list_add(tl, nb, ncnt, q + node_step<TX, TY>(d))) sl[Ln] = (lb & ~3u) | L_ACTIVE;
+                    }
+                }
+            };
+            constexpr int MAXC = (S::NT + kBlock - 1) / kBlock;
+            int cq[MAXC];
+            int nc = 0;
             for (int i = threadIdx.x; i < ncur; i += kBlock) {
                 const int q = tl.list[cb][i];
                 tl.flag[cb][q] = 0u;
@@ -312,24 +354,30 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
                 const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
                 const T cur = sphi[Lq];
                 if (pt < inf && cur - pt <= eps) {
-                    // converged: joins Source; FAR neighbours become active
-                    sl[Lq] = (sl[Lq] & ~3u) | L_CONV;
-                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
-#pragma unroll
-                    for (int d = 0; d < 2 * ND; ++d) {
-                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                        const uint8_t lb = sl[Ln];
-                        if (edge & (1 << d)) {
-                            if ((open & (1 << d)) && (lb & 3u) == L_FAR) fm |= 1 << d;
-                        } else if (!(lb & kOut) && (lb & 3u) == L_FAR && (lb & kPass)) {
-                            if (list_add(tl, nb, ncnt, q + node_step<TX, TY>(d))) sl[Ln] = (lb & ~3u) | L_ACTIVE;
-                        }
-                    }
+                    converge(q, Lq, x, y, z);
                 } else if (!(pt < inf)) {
                     sl[Lq] = (sl[Lq] & ~3u) | L_FAR;
                 } else {
-                    if (pt < cur) sphi[Lq] = pt;
-                    list_add(tl, nb, ncnt, q);
+                    sphi[Lq] = pt;  // pt < cur - eps
+                    if (TWO_PHASE) {
+                        const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
+#pragma unroll
+                        for (int d = 0; d < 2 * ND; ++d)
+                            if (!(edge & (1 << d))) schg[cb][q + node_step<TX, TY>(d)] = 1;
+                        cq[nc++] = q;
+                    } else {
+                        list_add(tl, nb, ncnt, q);
+                    }
+                }
+            }
+            if (TWO_PHASE) {
+                __syncthreads();
+                for (int j = 0; j < nc; ++j) {
+                    const int q = cq[j];
+                    int x, y, z, Lq;
+                    node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+                    if (!schg[cb][q]) converge(q, Lq, x, y, z);
+                    else list_add(tl, nb, ncnt, q);
                 }
             }
             __syncthreads();
@@ -803,16 +851,16 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     TileWs w = tile_layout(ws, b.n, b.ntiles, b.inst.size(), sizeof(Inst<T>));
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * b.n + 64;
     // Inner iterations per tile visit.  In 2D an update visit stops after the
-    // iterations a front needs to cross the tile along an axis (two per node:
-    // one to take a value, one to confirm it): the front still advances a
-    // tile per launch, and no visit holds its launch for a diagonal crossing
-    // (2D lognormal 4096^2, 16 x 16 tiles: update 34 -> 21 ms).  In 3D the
-    // cut visits leave more to the remedy than they save (256^3 maze), so
-    // update and remedy visits run until their lists empty (4 x the sum of
-    // the sides is a safety cap).
+    // iterations a front needs to cross the tile along an axis (one per node
+    // with the 2D two-phase iteration): the front still advances a tile per
+    // launch, and no visit holds its launch for a diagonal crossing (2D
+    // lognormal 4096^2, 16 x 16 tiles: update 34 -> 19 ms).  In 3D the cut
+    // visits leave more to the remedy than they save (256^3 maze), so update
+    // and remedy visits run until their lists empty (4 x the sum of the sides
+    // is a safety cap).
     const int side = std::max(c.tx, std::max(c.ty, c.tz));
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
-    const int inner_upd = o.inner_iters > 0 ? o.inner_iters : (b.nd == 2 ? 2 * side : inner);
+    const int inner_upd = o.inner_iters > 0 ? o.inner_iters : (b.nd == 2 ? side : inner);
     const int ntiles = static_cast<int>(b.ntiles);
     int64_t launched = 0;
 
