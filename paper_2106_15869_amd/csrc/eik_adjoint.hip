@@ -193,9 +193,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
     __shared__ int s_wlen[kSub];
     const int n = list_open(a, s_len, s_wlen);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) a.ctl->iters3 += 1;
-    const TList src = a.ordered ? a.work : a.cur;
+    const bool direct = list_direct(a, n);  // a short list is drained where it is
+    const bool from_work = a.ordered && !direct;
+    const TList src = from_work ? a.work : a.cur;
     const int k = blockIdx.x & (kSub - 1);
-    const int len = a.ordered ? s_wlen[k] : s_len[k];
+    const int len = from_work ? s_wlen[k] : s_len[k];
     constexpr int SY = S::LX, SZ = S::LX * S::LY;
     unsigned long long visits = 0;
     for (;;) {
@@ -204,11 +206,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
             if (tt >= 0) {
-                if (a.ordered) {
+                if (from_work) {
                     // the split moved the key and dirty faces into the work entry
                     s_key = src.key[idx];
                     s_mask = src.mask[idx];
                 } else {
+                    if (direct) {
+                        s_key = a.key_cur[tt];
+                        a.key_cur[tt] = kNoKey;
+                    }
                     s_mask = a.mask_cur[tt];
                     a.mask_cur[tt] = 0u;
                 }

@@ -251,6 +251,10 @@ __device__ __forceinline__ int list_open(const Sched& a, int* s_len, int* s_wlen
     return n;
 }
 
+// Ordered mode with a current list of n tiles: whether the launch drains the
+// current list itself (k_tile_split moved nothing to the work list).
+__device__ __forceinline__ bool list_direct(const Sched& a, int n) { return a.ordered && n <= a.order_min; }
+
 // Next entry of sub-list k for this workgroup (-1 when drained).  Lane 0
 // fetches; the value is broadcast through LDS.
 __device__ __forceinline__ int list_fetch(const TList& L, int k, int len, int* s_slot) {
@@ -344,6 +348,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     // blocks past the list's end have nothing to do; an empty list stays
     // empty (nothing is processed that could queue tiles)
     if (n == 0 || (blockIdx.x > 0 && static_cast<int>(blockIdx.x) * kBlock >= n)) return;
+    // A list no longer than order_min goes to the launch whole: the consumer
+    // then drains the current list itself (list_direct) and only the next
+    // list's histogram has to start at zero.
+    if (n <= a.order_min) {
+        if (blockIdx.x == 0)
+            for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_next[j] = 0u;
+        return;
+    }
     const int thr = order_threshold(a, n, &s_thr);
     // The deferred tiles are the listed tiles with key bins above thr, and
     // the current histogram counts the listed tiles by key bin, so the next

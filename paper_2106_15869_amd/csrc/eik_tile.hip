@@ -504,19 +504,25 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
     __shared__ int s_wlen[kSub];
     const int n = list_open(a, s_len, s_wlen);
     launch_stats(a, n);
-    const TList src = a.ordered ? a.work : a.cur;
+    const bool direct = list_direct(a, n);  // a short list is drained where it is
+    const bool from_work = a.ordered && !direct;
+    const TList src = from_work ? a.work : a.cur;
     const int k = blockIdx.x & (kSub - 1);
-    const int len = a.ordered ? s_wlen[k] : s_len[k];
+    const int len = from_work ? s_wlen[k] : s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
     for (;;) {
         if (threadIdx.x == 0) {
             const int e = atomicAdd(src.fetch + k * kPad, 1);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
-            if (e < len && a.ordered) {
+            if (e < len && from_work) {
                 // the split moved the key and dirty faces into the work entry
                 s_key = src.key[idx];
                 s_mask = src.mask[idx];
+            } else if (tt >= 0 && direct) {
+                // the tile leaves the current list: its key goes with it
+                s_key = a.key_cur[tt];
+                a.key_cur[tt] = kNoKey;
             }
             s_slot = tt;
         }
@@ -532,7 +538,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
         uint32_t mask_in = 0;
         if (threadIdx.x == 0) {
-            if (!a.ordered) {
+            if (!from_work) {
                 // written by the previous launch; no writer during this one
                 mask_in = a.mask_cur[t];
                 a.mask_cur[t] = 0u;
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
             s_face = 0;
             s_evals = 0;
             s_written = 0;
-            if (!a.ordered) s_mask = mask_in;
+            if (!from_work) s_mask = mask_in;
             tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
         }
         __syncthreads();
