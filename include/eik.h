@@ -126,7 +126,9 @@ typedef struct {
     eik_dtype dtype;           /* element type of F / phi (default float32) */
     eik_variant variant;       /* default EIK_VARIANT_TILE */
     int32_t tile[3];           /* tile extents (z, y, x); 0 = library default
-                                  (16 x 16 in 2D, 8^3 in 3D) */
+                                  (8^3 in 3D; in 2D 16 x 16, with the update
+                                  step on 32 x 32); an explicit shape applies
+                                  to every step */
     int32_t inner_iters;       /* tile variant: inner iterations per tile visit; 0 = default:
                                   4 x the sum of the tile sides, except the
                                   longest side in the 2D update step */
