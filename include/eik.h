@@ -264,7 +264,8 @@ typedef struct {
  *   phi_scratch  device, N elements; overwritten by the timed solves
  *   opt          in: dtype, stream, workspace (used when large enough, else
  *                the library allocates); out: tile and inner_iters of the
- *                fastest candidate, variant = EIK_VARIANT_TILE
+ *                fastest candidate, variant = EIK_VARIANT_TILE (tile
+ *                (0, 0, 0) when the default shapes won)
  *   report       host, nullable: up to report_cap timed candidates;
  *                *n_report (nullable) receives the count written
  * The choice is cached per (ndim, dtype, log2 of N) for the life of the

@@ -29,10 +29,13 @@ std::map<std::tuple<int, int, int>, Choice>& tune_cache() {
     return m;
 }
 
+// A zero tile is the library default: in 2D that runs the update step on
+// 32 x 32 tiles and detection/remedy on 16 x 16, a pairing no explicit shape
+// gives.
 std::vector<Choice> candidates(int nd) {
     if (nd == 2)
-        return {{{1, 16, 16}, 0}, {{1, 16, 16}, 48}, {{1, 32, 32}, 0}, {{1, 16, 64}, 0},
-                {{1, 8, 32}, 0},  {{1, 64, 64}, 0}};
+        return {{{0, 0, 0}, 0}, {{1, 16, 16}, 0}, {{1, 16, 16}, 48}, {{1, 32, 32}, 0},
+                {{1, 16, 64}, 0}, {{1, 8, 32}, 0}, {{1, 64, 64}, 0}};
     return {{{8, 8, 8}, 0}, {{8, 8, 8}, 16}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
 }
 
