@@ -888,11 +888,9 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     // visits leave more to the remedy than they save (256^3 maze), so update
     // and remedy visits run until their lists empty (4 x the sum of the sides
     // is a safety cap).
-    const int side = std::max(c.tx, std::max(c.ty, c.tz));
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (c.tx + c.ty + c.tz);
     const int side_u = std::max(cu.tx, std::max(cu.ty, cu.tz));
     const int inner_upd = o.inner_iters > 0 ? o.inner_iters : (b.nd == 2 ? side_u : inner);
-    (void)side;
     const int ntiles_u = static_cast<int>(B2.ntiles);
     int64_t launched = 0;
 
