@@ -262,14 +262,17 @@ typedef struct {
  * work-group size, and the tile shape plays that role here.
  *   F, ndim, dims, h, sources, n_sources, eps  as eik_solve
  *   phi_scratch  device, N elements; overwritten by the timed solves
- *   opt          in: dtype, stream, workspace (used when large enough, else
- *                the library allocates); out: tile and inner_iters of the
+ *   opt          in: dtype, stream, spacing (per-axis spacing times only the
+ *                default shapes, the only ones it runs on), workspace (used
+ *                when large enough, else the library allocates); out: tile
+ *                and inner_iters of the
  *                fastest candidate, variant = EIK_VARIANT_TILE (tile
  *                (0, 0, 0) when the default shapes won)
  *   report       host, nullable: up to report_cap timed candidates;
  *                *n_report (nullable) receives the count written
- * The choice is cached per (ndim, dtype, log2 of N) for the life of the
- * process: a later call for the same class times nothing and reports 0
+ * The choice is cached per (ndim, dtype, log2 of N, per-axis spacing or
+ * not) for the life of the process: a later call for the same class times
+ * nothing and reports 0
  * entries.  Errors as eik_solve.
  */
 eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,

@@ -506,14 +506,16 @@ def adjoint_batch(F, phi, shapes, h, sources, dL_dphi, *, out=None, workspace=No
     return (res, st.to_dict()) if stats else res
 
 
-def tune(F, h: float, sources, eps: float = 0.0, *, stream=None, workspace=None):
+def tune(F, h: Optional[float], sources, eps: float = 0.0, *, stream=None, workspace=None,
+         spacing: Optional[Sequence[float]] = None):
     """Time the tile-variant candidates on this problem (eik_tune) and return
     {"tile": (z, y, x), "inner_iters": k, "candidates": [...]} -- pass tile and
-    inner_iters to solve().  Cached per (ndim, dtype, log2 N) for the process;
-    a cached answer reports no candidates."""
+    inner_iters to solve().  Cached per (ndim, dtype, log2 N, per-axis spacing
+    or not) for the process; a cached answer reports no candidates."""
     torch = _torch()
     _check_device_tensor(F, "F")
-    opt = make_options(_dtype_code(F))
+    opt = make_options(_dtype_code(F), spacing=spacing)
+    h = 1.0 if h is None and spacing is not None else h
     s = stream if stream is not None else torch.cuda.current_stream(F.device)
     opt.stream = s.cuda_stream
     if workspace is not None:

@@ -1,6 +1,7 @@
 // eik_tune: per-problem choice of the tile shape and inner-iteration cap of
 // the tile variant, by timing candidates with HIP events on the caller's
-// stream.  Choices are cached per (ndim, dtype, log2 N) for the process.
+// stream.  Choices are cached per (ndim, dtype, log2 N, per-axis spacing
+// or not) for the process.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,19 +25,31 @@ struct Choice {
 };
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, Choice>& tune_cache() {
-    static std::map<std::tuple<int, int, int>, Choice> m;
+std::map<std::tuple<int, int, int, int>, Choice>& tune_cache() {
+    static std::map<std::tuple<int, int, int, int>, Choice> m;
     return m;
 }
 
 // A zero tile is the library default: in 2D that runs the update step on
 // 32 x 32 tiles and detection/remedy on 16 x 16, a pairing no explicit shape
-// gives.
-std::vector<Choice> candidates(int nd) {
+// gives.  Per-axis spacing (Eq 5) is supported on the default shapes only
+// (16 x 16 in 2D, 8^3 in 3D), so only those are timed then.
+std::vector<Choice> candidates(int nd, bool aniso) {
+    std::vector<Choice> all;
     if (nd == 2)
-        return {{{0, 0, 0}, 0}, {{1, 16, 16}, 0}, {{1, 16, 16}, 48}, {{1, 32, 32}, 0},
-                {{1, 16, 64}, 0}, {{1, 8, 32}, 0}, {{1, 64, 64}, 0}};
-    return {{{8, 8, 8}, 0}, {{8, 8, 8}, 16}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
+        all = {{{0, 0, 0}, 0}, {{1, 16, 16}, 0}, {{1, 16, 16}, 48}, {{1, 32, 32}, 0},
+               {{1, 16, 64}, 0}, {{1, 8, 32}, 0}, {{1, 64, 64}, 0}};
+    else
+        all = {{{8, 8, 8}, 0}, {{8, 8, 8}, 16}, {{4, 8, 8}, 0}, {{4, 4, 16}, 0}, {{8, 8, 16}, 0}};
+    if (!aniso) return all;
+    std::vector<Choice> out;
+    for (const Choice& c : all) {
+        const bool zero = c.tile[0] == 0 && c.tile[1] == 0 && c.tile[2] == 0;
+        const bool def = nd == 2 ? (c.tile[1] == 16 && c.tile[2] == 16)
+                                 : (c.tile[0] == 8 && c.tile[1] == 8 && c.tile[2] == 8);
+        if (zero || def) out.push_back(c);
+    }
+    return out;
 }
 
 struct Events {
@@ -73,8 +86,11 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     int64_t n = 1;
     for (int k = 0; k < ndim; ++k) n *= dims[k] > 0 ? dims[k] : 0;
     if (n < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every dim must be >= 1");
+    bool aniso = false;
+    for (int k = 0; k < 3; ++k) aniso |= opt->spacing[k] != 0.0;
     const auto key = std::make_tuple(static_cast<int>(ndim), static_cast<int>(opt->dtype),
-                                     static_cast<int>(std::floor(std::log2(static_cast<double>(n)))));
+                                     static_cast<int>(std::floor(std::log2(static_cast<double>(n)))),
+                                     static_cast<int>(aniso));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = tune_cache().find(key);
@@ -88,7 +104,7 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     eik_options base = *opt;
     base.variant = EIK_VARIANT_TILE;
     base.stats = nullptr;
-    const std::vector<Choice> cand = candidates(ndim);
+    const std::vector<Choice> cand = candidates(ndim, aniso);
     size_t need = 0;
     for (const Choice& c : cand) {
         eik_options q = base;

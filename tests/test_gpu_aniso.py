@@ -85,3 +85,24 @@ def test_equal_spacing_matches_isotropic():
     a = eik.solve(F, P.h, P.sources).cpu().numpy()
     b = eik.solve(F, None, P.sources, spacing=(P.h, P.h)).cpu().numpy()
     assert np.max(np.abs(a - b)) <= 1e-13 * a.max()
+
+
+@pytest.mark.parametrize("case", [_cases()[0], _cases()[3]], ids=lambda c: c[0])
+def test_tune_with_spacing(case):
+    """eik_tune with per-axis spacing times only the shapes that support it,
+    its choice solves within the float32 gate, and the isotropic problem of
+    the same size class is tuned on its own (separate cache entry)."""
+    name, F, sp, src = case
+    print(f"[case] tune aniso {name}", flush=True)
+    Fd = dev(F.astype(np.float32))
+    t = eik.tune(Fd, None, src, spacing=sp)
+    default = (1, 16, 16) if F.ndim == 2 else (8, 8, 8)
+    assert t["candidates"], "first call for this class times candidates"
+    assert all(c["tile"] in {(0, 0, 0), default} for c in t["candidates"])
+    got = eik.solve(Fd, None, src, spacing=sp, tile=t["tile"], inner_iters=t["inner_iters"]).cpu().numpy()
+    ref = oracle.fmm(F.astype(np.float32).astype(np.float64), 1.0, src, spacing=sp)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.max(np.abs(got[fin] - ref[fin])) <= TOL[np.float32] * ref[fin].max()
+    iso = eik.tune(Fd, 1.0, src)
+    assert iso["candidates"] and any(c["tile"] not in {(0, 0, 0), default} for c in iso["candidates"])
