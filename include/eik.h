@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 4
+#define EIK_ABI_VERSION 5
 
 typedef enum {
     EIK_OK = 0,
@@ -76,8 +76,10 @@ enum {
     /* Diagnostic: return after the update step, skipping the remedy step
        (not with EIK_VARIANT_FIM, which has none). */
     EIK_FLAG_SKIP_REMEDY = 2u,
-    /* Enqueue only: no host synchronisation, no F check, no stats.  The caller
-       must pass a workspace and synchronise the stream itself. */
+    /* Enqueue only: no host synchronisation, no stats.  The caller must pass
+       a workspace and an explicit max_iters, which every loop then runs in
+       full (launches after convergence find empty lists and return at once);
+       eik_async_status reads the outcome once the stream has run the work. */
     EIK_FLAG_ASYNC = 4u,
     /* Bracket every kernel launch with HIP events on the solve's stream and
        report per-kind device time in eik_stats (adds host overhead). */
@@ -278,6 +280,26 @@ typedef struct {
 eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
                     int64_t n_sources, double eps, void* phi_scratch, eik_options* opt,
                     eik_tune_entry* report, int32_t report_cap, int32_t* n_report);
+
+/*
+ * eik_async_status -- outcome of the last call enqueued with EIK_FLAG_ASYNC
+ * on this workspace (eik_solve, eik_solve_batch, eik_adjoint,
+ * eik_adjoint_batch; also valid after replaying a graph captured from such
+ * calls).  Waits for `stream` (hipStream_t, NULL: the default stream) and
+ * reads the control word the call's kernels wrote at the start of the
+ * workspace.  Algorithm 2 loops "while the list is not empty"; an
+ * asynchronous call cannot stop early, so it runs its launch budget and a
+ * last kernel per loop records whether the list it would drain next is empty.
+ *   workspace  device, the workspace passed to that call (256-byte aligned)
+ * Returns EIK_OK when every loop emptied its lists within max_iters launches,
+ * EIK_ERR_NO_CONVERGENCE when one did not (the output then holds the current
+ * iterate, an upper bound of the solution; enqueue again with a larger
+ * max_iters), EIK_ERR_INVALID_ARGUMENT when a forward solve found F negative
+ * or not finite, EIK_ERR_DEVICE on a HIP error.  The word is reset by the
+ * next call on the workspace.  Not meaningful after synchronous calls, which
+ * return their status directly.
+ */
+eik_status eik_async_status(const void* workspace, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_status_string(eik_status s);

@@ -264,8 +264,10 @@ def fim(F, h: float, sources, values=None, eps: float = 0.0, max_iters: Optional
     return phi, dict(zip(FIM_STAT_NAMES, (int(v) for v in stats)))
 
 
-def adjoint(F, h: float, sources, phi, dL_dphi, values=None, spacing=None):
-    """dL/dF for a loss L(phi), by reverse sweep in acceptance order (float64)."""
+def adjoint(F, h: float, sources, phi, dL_dphi, values=None, spacing=None, return_lambda: bool = False):
+    """dL/dF for a loss L(phi), by reverse sweep in acceptance order (float64).
+    With return_lambda, also the adjoint state lambda (lambda = dL/dphi +
+    M^T lambda, the multiplier of each node's equation)."""
     lib = _load()
     if not hasattr(lib, "eo_adjoint"):
         raise NotImplementedError("oracle adjoint not built")
@@ -274,8 +276,9 @@ def adjoint(F, h: float, sources, phi, dL_dphi, values=None, spacing=None):
     p = np.ascontiguousarray(np.asarray(phi), dtype=np.float64)
     g = np.ascontiguousarray(np.asarray(dL_dphi), dtype=np.float64)
     out = np.empty_like(F64)
+    lam = np.empty_like(F64) if return_lambda else None
     rc = lib.eo_adjoint_a(F64.ndim, _ptr(dims), float(h), None if sp is None else _ptr(sp), _ptr(F64),
-                          _ptr(src), len(src), _ptr(p), _ptr(g), _ptr(out), None)
+                          _ptr(src), len(src), _ptr(p), _ptr(g), _ptr(out), None if lam is None else _ptr(lam))
     if rc:
         raise ValueError("eo_adjoint failed: %d" % rc)
-    return out
+    return (out, lam) if return_lambda else out

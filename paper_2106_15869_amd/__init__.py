@@ -11,6 +11,7 @@ Functions mirror the C entry points:
 * ``eik_apply_local``  one dense pass of the exact Godunov local solve.
 * ``eik_adjoint``      dL/dF at a converged solution.
 * ``eik_solve_batch`` / ``eik_adjoint_batch``  the same for many grids at once.
+* ``eik_async_status`` whether asynchronous (graph-captured) work converged.
 * ``eik_workspace_size``, ``eik_status_string``, ``eik_abi_version``.
 
 ``solve`` / ``apply_local`` / ``adjoint`` / ``solve_batch`` / ``adjoint_batch``
@@ -41,7 +42,7 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 4
+EIK_ABI_VERSION = 5
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
@@ -55,7 +56,7 @@ VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
            "eik_adjoint", "eik_adjoint_workspace_size", "eik_status_string", "eik_last_error",
            "eik_abi_version", "eik_solve_batch", "eik_batch_workspace_size", "eik_adjoint_batch",
-           "eik_adjoint_batch_workspace_size", "eik_tune")
+           "eik_adjoint_batch_workspace_size", "eik_tune", "eik_async_status")
 
 
 KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
@@ -160,6 +161,8 @@ def _load():
     lib.eik_adjoint_batch.argtypes = [P, P, i32, IP, i32, P, P, P, OP]
     lib.eik_adjoint_batch_workspace_size.restype = ctypes.c_size_t
     lib.eik_adjoint_batch_workspace_size.argtypes = [i32, IP, i32, OP]
+    lib.eik_async_status.restype = ctypes.c_int
+    lib.eik_async_status.argtypes = [P, P]
     if lib.eik_abi_version() != EIK_ABI_VERSION:
         raise ImportError(f"{LIB_PATH} has ABI version {lib.eik_abi_version()}, this binding expects "
                           f"{EIK_ABI_VERSION}: rebuild it with `python -m paper_2106_15869_amd.build`")
@@ -223,6 +226,22 @@ def eik_status_string(status: int) -> str:
 
 def eik_abi_version() -> int:
     return int(_load().eik_abi_version())
+
+
+def async_status(workspace, stream=None) -> int:
+    """eik_async_status: outcome of the last asynchronous call (or graph
+    replay) on `workspace` -- EIK_OK, EIK_ERR_NO_CONVERGENCE (a loop used up
+    its launch budget) or EIK_ERR_INVALID_ARGUMENT (bad F).  Waits for the
+    stream."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+    with torch.cuda.device(workspace.device):
+        return int(_load().eik_async_status(workspace.data_ptr(), s.cuda_stream))
+
+
+def check_async(workspace, stream=None) -> None:
+    """Raise EikError unless the last asynchronous call on `workspace` converged."""
+    _check(async_status(workspace, stream))
 
 
 # ---------------------------------------------------------------------------

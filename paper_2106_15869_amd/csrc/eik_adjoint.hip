@@ -502,7 +502,7 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     };
     int64_t nl = 0;
     eik_status rc = run_loop(step, [&](int64_t t) { return w.q.count_of(static_cast<int>(t % 3)); }, kSub * kPad, cap,
-                             async, s, &nl);
+                             async, s, &nl, w.ctl);
     launched += (ordered ? 2 : 1) * nl;
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] {
         hipLaunchKernelGGL(k_adj_final<T>, dim3(dense), dim3(kBlock), 0, s, static_cast<int>(b.n),

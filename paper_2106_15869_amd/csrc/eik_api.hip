@@ -277,7 +277,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>&
                            : launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s);
             });
         },
-        counts, kNodeSegs, cap, async, s, &n2);
+        counts, kNodeSegs, cap, async, s, &n2, w.ctl);
     launched += (fim ? 2 : per_iter) * n2;
     if (rc == EIK_OK && !fim && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // STEP 3a: whole-grid check into list 0
@@ -290,7 +290,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>&
                 return timed(prof, EIK_KERNEL_REMEDY,
                              [&] { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); });
             },
-            counts, kNodeSegs, cap, async, s, &n3);
+            counts, kNodeSegs, cap, async, s, &n3, w.ctl);
         launched += per_iter * n3;
     }
     if (async) return rc;
@@ -616,6 +616,21 @@ EIK_API eik_status eik_adjoint_batch(const void* F, const void* phi, int32_t ndi
     return adjoint_solve<float>(b, static_cast<const float*>(F), static_cast<const float*>(phi),
                                 static_cast<const float*>(dL_dphi), static_cast<float*>(dL_dF_out), o, ws, s,
                                 o.stats);
+}
+
+EIK_API eik_status eik_async_status(const void* workspace, void* stream) {
+    g_last_error.clear();
+    if (!workspace) return fail(EIK_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    // every workspace layout starts with the control block
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, workspace, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c.err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
+    if (c.open_lists) return fail(EIK_ERR_NO_CONVERGENCE, "a loop used up its launch budget with work left");
+    return EIK_OK;
 }
 
 EIK_API const char* eik_status_string(eik_status s) {

@@ -138,12 +138,16 @@ inline unsigned long long blk_sum(const unsigned long long* blk, int field, int 
 // sum is read back after every chunk while the next chunk is already queued,
 // so the device never idles on the host.  Returns EIK_OK, or
 // EIK_ERR_NO_CONVERGENCE after max_iters steps; *steps receives the number of
-// steps enqueued.
+// steps enqueued.  Asynchronously (no host round trip) exactly max_iters
+// steps are enqueued, launches after convergence finding empty lists, and a
+// last kernel records in ctl->open_lists whether work was left over (read
+// back later by eik_async_status).
 template <typename StepFn, typename CountsFn>
 inline eik_status run_loop(StepFn step, CountsFn counts, int nseg, int64_t max_iters, bool async,
-                           hipStream_t s, int64_t* steps) {
+                           hipStream_t s, int64_t* steps, Ctl* ctl) {
     if (async) {
         for (int64_t t = 0; t < max_iters; ++t) HIP_TRY(step(t));
+        HIP_TRY(launch_loop_status(ctl, counts(max_iters), nseg, s));
         *steps = max_iters;
         return EIK_OK;
     }

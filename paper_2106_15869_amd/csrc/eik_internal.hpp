@@ -24,7 +24,8 @@ struct Ctl {
     int cnt[4];       // spare counters
     int err;          // bit 0: F negative or not finite
     int tag[2];       // remedy stamp tags, alternating by iteration parity
-    int pad;
+    int open_lists;   // asynchronous calls: nonzero when a loop used up its
+                      // launch budget with work still listed (k_loop_status)
     unsigned long long iters2, iters3, evals2, evals_det, evals_rem, remedy_init, max_active;
     unsigned long long visits2, visits3, inner2, inner3;
 };
@@ -151,5 +152,9 @@ template <typename T>
 hipError_t launch_fim(const GridDims& g, const NodeIter<T>& it, const Spacing<T>& h, T eps, hipStream_t s);
 hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
+// After the last budgeted launch of an asynchronous loop: sums the `nseg`
+// length words of the list the next launch would drain and records in
+// ctl->open_lists whether it is non-empty.
+hipError_t launch_loop_status(Ctl* ctl, const int* counts, int nseg, hipStream_t s);
 
 }  // namespace eik

@@ -573,12 +573,21 @@ __global__ void k_ctl_init(Ctl* ctl) {
     if (threadIdx.x == 0) {
         for (int k = 0; k < 4; ++k) ctl->cnt[k] = 0;
         ctl->err = 0;
+        ctl->open_lists = 0;
         ctl->tag[0] = 1;
         ctl->tag[1] = 1;
         ctl->iters2 = ctl->iters3 = ctl->evals2 = ctl->evals_det = ctl->evals_rem = 0;
         ctl->remedy_init = ctl->max_active = 0;
         ctl->visits2 = ctl->visits3 = ctl->inner2 = ctl->inner3 = 0;
     }
+}
+
+// Whether the list a loop would drain next still holds work (one block; the
+// length words of unused slots are zero).
+__global__ __launch_bounds__(kBlock) void k_loop_status(Ctl* ctl, const int* counts, int nseg) {
+    int any = 0;
+    for (int k = threadIdx.x; k < nseg; k += kBlock) any |= counts[k] != 0;
+    if (__syncthreads_or(any) && threadIdx.x == 0) ctl->open_lists = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,6 +724,11 @@ hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s) {
 
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_loop_status(Ctl* ctl, const int* counts, int nseg, hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_status, dim3(1), dim3(kBlock), 0, s, ctl, counts, nseg);
     return hipGetLastError();
 }
 

@@ -965,7 +965,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         [&](int64_t t) {
             return timed(prof, EIK_KERNEL_UPDATE, [&] { return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, s); });
         },
-        counts, kSub * kPad, cap, async, s, &n2);
+        counts, kSub * kPad, cap, async, s, &n2, w.ctl);
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
@@ -995,7 +995,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
                 }
                 return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(a, geom, eT, inner, s); });
             },
-            counts, kSub * kPad, cap, async, s, &n3);
+            counts, kSub * kPad, cap, async, s, &n3, w.ctl);
         launched += (ordered ? 2 : 1) * n3;
     }
     if (async) return rc;

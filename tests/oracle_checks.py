@@ -1,0 +1,96 @@
+"""Checks of GPU outputs that use the float64 oracle on the GPU's own result.
+
+fixed_point_ulps: how far a float32 solution is from being a fixed point of
+the exact local solve (Eq 4 / Eq 6), node by node, in float32 ulps.
+
+fp32_adjoint_bound / check_fp32_adjoint: rounding bound of a float32 adjoint,
+node by node.
+
+The GPU adjoint and the float64 oracle adjoint are compared on the SAME
+solution phi (the GPU's float32 output, upcast exactly).  Both then use the
+same upwind stencil at every node (the stencil is read off phi, the lower
+index winning a tie on both sides), so they solve the same linear system
+
+    lambda = g + M^T lambda,   dL/dF = D lambda,
+    M_{i,j_k} = c_ik = w_ik / W_i,  W_i = sum_k w_ik,  w_ik = phi_i - phi_{j_k},
+    D_i = -(h/F_i)^2 / (F_i W_i)
+
+(the derivative of the Eq 4 / Eq 6 fixed point), and differ only by the
+float32 rounding of the GPU's arithmetic.  With u = 2^-24:
+
+* a coefficient c_ik carries at most (3 + ND) u: w_ik one rounding (two more
+  with per-axis spacing), W_i ND - 1, the division one;
+* the GPU recomputes lambda_j = g_j + sum_i c_ij lambda_i from the final
+  lambda_i (a node is recomputed whenever one of its inputs changes), one
+  rounding per product and up to 2 ND additions;
+* so, with e_j the error of lambda_j and kappa = (7 + 2 ND) u,
+      e_j <= sum_i c_ij e_i + kappa (|g_j| + sum_i c_ij |lambda_i|),
+  and by induction over the causal order e_j <= kappa nu_j, where
+      labs = |g| + M^T labs   (the adjoint of |g|) and
+      nu   = labs + M^T nu    (the adjoint of labs);
+  nu_j sums every contribution to lambda_j weighted by its path length + 1;
+* dL/dF_j = D_j lambda_j adds at most 12 u |D_j| labs_j (D_j's own roundings
+  and the product).
+
+Hence |dL/dF_gpu - dL/dF_oracle| <= u |D| ((7 + 2 ND) nu + 12 labs) per node,
+computed here with two more oracle adjoint solves (to first order in u; the
+oracle's own float64 rounding is 2^29 times smaller).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+U32 = 2.0 ** -24
+
+
+def fixed_point_ulps(F, h, phi, sources) -> np.ndarray:
+    """|phi_i - G_i(phi)| / ulp_f32(phi_i) over finite non-source nodes with
+    F > 0, G evaluated in float64 by the oracle on the float32 values.
+
+    A float32 run of Algorithm 2 with eps = 0 ends where no node's float32
+    update lies below its value and every value is a float32 update of
+    neighbour values at least as large; the float32 root is monotone in its
+    inputs only up to its own rounding, so the distance is a few ulps, not
+    zero (the oracle's float32 emulation of Algorithm 2 ends at up to 2.94 ulp
+    on a 48^3 maze, where H = 1000 in the obstacles, and 0.8 ulp on smooth
+    fields)."""
+    F64 = np.asarray(F, dtype=np.float64)
+    p = np.asarray(phi)
+    G = oracle.apply_local(F64, h, p.astype(np.float64))
+    m = np.isfinite(p) & (F64 > 0)
+    m.flat[np.asarray(sources, dtype=np.int64)] = False
+    ulp = np.spacing(np.abs(p[m]).astype(np.float32)).astype(np.float64)
+    return np.abs(p[m].astype(np.float64) - G[m]) / ulp
+
+
+def fp32_adjoint_bound(F, h, sources, phi, g, spacing=None) -> np.ndarray:
+    """Per-node bound on |float32 GPU adjoint - float64 oracle adjoint|, both on
+    the solution `phi`, for the loss gradient `g` (see the module docstring)."""
+    nd = np.ndim(F)
+    F64 = np.asarray(F, dtype=np.float64)
+    p = np.asarray(phi, dtype=np.float64)
+    ga = np.abs(np.asarray(g, dtype=np.float64))
+    d_abs, labs = oracle.adjoint(F64, h, sources, p, ga, spacing=spacing, return_lambda=True)
+    d_nu = oracle.adjoint(F64, h, sources, p, labs, spacing=spacing)
+    return U32 * ((7 + 2 * nd) * np.abs(d_nu) + 12.0 * np.abs(d_abs))
+
+
+def check_fp32_adjoint(got, F, h, sources, phi, g, spacing=None, label=""):
+    """Assert the float32 adjoint `got` matches the oracle adjoint on the same
+    phi within the per-node bound; returns (max relative error, max error /
+    bound) for the record."""
+    want = oracle.adjoint(np.asarray(F, dtype=np.float64), h, sources, np.asarray(phi, dtype=np.float64),
+                          np.asarray(g, dtype=np.float64), spacing=spacing)
+    bound = fp32_adjoint_bound(F, h, sources, phi, g, spacing=spacing)
+    got = np.asarray(got, dtype=np.float64)
+    err = np.abs(got - want)
+    bad = err > bound + 1e-300
+    scale = max(float(np.abs(want).max()), 1e-300)
+    ratio = float(np.max(err / np.maximum(bound, 1e-300)))
+    print(f"[adjoint{label}] max|err| {err.max():.3e} = {err.max() / scale:.3e} of max|dL/dF|; "
+          f"max err/bound {ratio:.3e}; nodes over the bound {int(bad.sum())}", flush=True)
+    assert not bad.any(), (int(bad.sum()), float(err[bad].max()), float(bound[bad].min()))
+    return err.max() / scale, ratio

@@ -279,3 +279,12 @@ def test_spacing_rejected_for_batches(lib):
     src = np.array([0], dtype=np.int64)
     rc = lib.eik_solve_batch(0x1000, 2, _inst([(8, 8)]), 1, src.ctypes.data, 0.0, 0x2000, ctypes.byref(o))
     assert rc == eik.EIK_ERR_UNSUPPORTED
+
+
+def test_async_status_rejects_bad_workspace(lib):
+    """eik_async_status validates its workspace pointer on the host, before
+    any device call."""
+    assert lib.eik_async_status(None, None) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert b"NULL" in lib.eik_last_error()
+    assert lib.eik_async_status(0x1010, None) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert b"aligned" in lib.eik_last_error()

@@ -13,6 +13,7 @@ import pytest
 import oracle
 import workloads as W
 from tests import helpers as H
+from tests.oracle_checks import check_fp32_adjoint
 
 torch = pytest.importorskip("torch")
 eik = pytest.importorskip("paper_2106_15869_amd")
@@ -42,10 +43,16 @@ def receiver_seed(P, k=12, seed=0):
     return g
 
 
-# float32: the weights come from differences of neighbouring phi values (up to
-# ~50 here), so their relative error is about ulp(50) / (h/F) ~ 1e-5.
-@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-13), (np.float32, 1e-4)])
-def test_strip_closed_form(dtype, tol):
+# Per node j of the strip the GPU's weight is w_j = phi_j - phi_{j-1} from its
+# float32 solution, where phi_j = fl(phi_{j-1} + H_j) with H_j = fl(h/F_j):
+# w_j differs from h/F_j by at most ulp(phi_j)/2 + ulp(H_j)/2, the square of
+# H_j in D_j = -H_j^2/(F_j w_j) adds 2 ulp(H_j)/2, and D_j and the product with
+# lambda (= 1 exactly on the path: every coefficient is w/w) about 8
+# roundings.  So the float32 tolerance per node is
+# |want_j| ((ulp(phi_j) + 3 ulp(H_j)) / (2 H_j) + 8 u); float64: 1e-13 of the
+# largest value.
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_strip_closed_form(dtype):
     r = np.random.default_rng(5)
     n = 300
     F = np.exp(r.uniform(-1, 1, size=(1, n)))
@@ -56,7 +63,16 @@ def test_strip_closed_form(dtype, tol):
     Fq = F.astype(dtype).astype(np.float64)
     want = np.zeros(n)
     want[41:251] = -0.25 / Fq[0, 41:251] ** 2
-    assert np.max(np.abs(d[0] - want)) <= tol * np.max(np.abs(want))
+    if dtype == np.float64:
+        assert np.max(np.abs(d[0] - want)) <= 1e-13 * np.max(np.abs(want))
+        return
+    phi = oracle.fmm(Fq, 0.25, [40])[0]
+    H32 = (np.float32(0.25) / Fq[0].astype(np.float32)).astype(np.float64)
+    ulp = lambda v: np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)  # noqa: E731
+    tol = np.abs(want) * ((ulp(phi) + 3 * ulp(H32)) / (2 * H32) + 8 * 2.0 ** -24)
+    err = np.abs(d[0] - want)
+    print(f"[strip f32] max err/tol {np.max(err[41:251] / tol[41:251]):.3f}", flush=True)
+    assert np.all(err <= tol)
 
 
 # A receiver on the first or last node of a tile whose upwind neighbour lies in
@@ -86,21 +102,25 @@ def _cases():
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("P", _cases(), ids=lambda P: P.name)
 def test_adjoint_matches_oracle(P, dtype):
+    """Node by node against the oracle's reverse sweep on the GPU's own
+    solution (same upwind stencils): float64 within 1e-9 of the largest
+    gradient, float32 within the derived rounding bound of each node
+    (tests/oracle_checks.py).  Against the oracle adjoint on the oracle's own
+    float64 solution, float32 within 1e-3 of the largest gradient wherever the
+    two solutions use the same stencil."""
     g = receiver_seed(P)
     phi_g, d_g = gpu_grad(P, dtype, g)
     Fq = P.F.astype(dtype).astype(np.float64)
+    if dtype == np.float64:
+        d_o = oracle.adjoint(Fq, P.h, P.sources, phi_g, g)
+        assert np.max(np.abs(d_g - d_o)) <= 1e-9 * np.max(np.abs(d_o))
+        return
+    check_fp32_adjoint(d_g, Fq, P.h, P.sources, phi_g, g, label=f" {P.name}")
     phi_o = oracle.fmm(Fq, P.h, P.sources)
     d_o = oracle.adjoint(Fq, P.h, P.sources, phi_o, g)
-    scale = np.max(np.abs(d_o))
-    if dtype == np.float64:
-        assert np.max(np.abs(d_g - d_o)) <= 1e-9 * scale
-    else:
-        # compare where both solutions use the same upwind stencil
-        same = np.all(H.upwind_signature(phi_g) == H.upwind_signature(phi_o), axis=0)
-        err = np.abs(d_g - d_o)[same]
-        assert err.max() <= 1e-3 * scale, (err.max() / scale, int((~same).sum()))
-        # and globally the gradients agree in norm
-        assert np.linalg.norm(d_g - d_o) <= 2e-2 * np.linalg.norm(d_o)
+    same = np.all(H.upwind_signature(phi_g) == H.upwind_signature(phi_o), axis=0)
+    err = np.abs(d_g - d_o)[same]
+    assert err.max() <= 1e-3 * np.max(np.abs(d_o)), (err.max() / np.max(np.abs(d_o)), int((~same).sum()))
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])

@@ -1,22 +1,32 @@
 """Full-size parity: the benchmark workloads at their real sizes, solved in the
 configuration bench.py times (default options), against the float64
-fast-marching oracle on every node.  Tolerance: 1e-5 x max phi (float32),
-identical +inf masks; plus the fixed-point residual of the GPU output computed
-from the defining equation."""
+fast-marching oracle on every node.
+
+Gates (float32):
+  * max |phi - phi_oracle| <= 1e-5 x max phi over finite nodes, identical
+    +inf masks (the oracle runs on the same float32-rounded F);
+  * per node, the output is a fixed point of the exact local solve (Eq 4 /
+    Eq 6, evaluated in float64 on the float32 values) to within 4 float32
+    ulps of the node's value -- the float32 root itself is monotone only up to
+    its rounding, and the oracle's float32 emulation of Algorithm 2 ends at
+    up to 2.94 ulp on a maze (tests/oracle_checks.py).
+Reported, not gated: the per-node relative error on the maze's free (F = 1)
+cells, whose values are far below the obstacle interiors that set max phi.
+"""
 
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from tests import helpers as H
+from tests.oracle_checks import check_fp32_adjoint, fixed_point_ulps
 
 torch = pytest.importorskip("torch")
 eik = pytest.importorskip("paper_2106_15869_amd")
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-
+MAX_ULPS = 4.0
 
 SCHEDULE = {"node": dict(variant="node"), "tile": dict(variant="tile"), "fim": dict(variant="fim"),
             "fifo": dict(variant="tile", fifo=True)}
@@ -26,25 +36,30 @@ def _check(P, variant):
     print(f"[case] fullsize {P.name} {variant}", flush=True)
     F = torch.from_numpy(P.F).to(DEV)
     phi, st = eik.solve(F, P.h, P.sources, stats=True, **SCHEDULE[variant])
-    got = phi.cpu().numpy().astype(np.float64)
+    got = phi.cpu().numpy()
     print(f"[stats] {st}", flush=True)
     ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
     fin = np.isfinite(ref)
     assert np.array_equal(fin, np.isfinite(got))
-    err = np.abs(got[fin] - ref[fin])
+    err = np.abs(got[fin].astype(np.float64) - ref[fin])
     m = ref[fin].max()
-    print(f"[err] max {err.max() / m:.3e} of max phi; mean {err.mean() / m:.3e}", flush=True)
+    ulps = fixed_point_ulps(P.F, P.h, got, P.sources)
+    print(f"[err] max {err.max() / m:.3e} of max phi; mean {err.mean() / m:.3e}; "
+          f"fixed point: max {ulps.max():.2f} ulp, 99.99% {np.quantile(ulps, 0.9999):.2f} ulp", flush=True)
     assert err.max() <= 1e-5 * m
-    # per-node relative error on free cells, diagnostic only
+    assert ulps.max() <= MAX_ULPS
     return got, ref
 
 
 @pytest.mark.parametrize("variant", ["tile", "node", "fim", "fifo"])
 def test_maze_256(variant):
     P = W.maze_3d(256)
-    got, _ = _check(P, variant)
-    # float32 fixed point: the equation residual is a few ulps
-    assert H.equation_residual(P.F, P.h, got, P.sources) < 1e-5
+    got, ref = _check(P, variant)
+    free = (P.F == 1.0) & np.isfinite(ref)
+    free.flat[P.sources] = False
+    rel = np.abs(got[free].astype(np.float64) - ref[free]) / ref[free]
+    print(f"[free cells] per-node relative error: max {rel.max():.3e}, mean {rel.mean():.3e} "
+          f"over {int(free.sum())} F = 1 cells", flush=True)
 
 
 @pytest.mark.parametrize("variant", ["tile", "node", "fifo"])
@@ -53,26 +68,12 @@ def test_lognormal_4096(variant):
     _check(P, variant)
 
 
-def test_layered_192_forward_and_adjoint():
-    P = W.layered_3d(192)
-    got, ref = _check(P, "tile")
-    g = np.zeros(P.F.shape)
-    g.flat[P.receivers] = 1.0
-    F = torch.from_numpy(P.F).to(DEV)
-    phi = torch.from_numpy(got.astype(np.float32)).to(DEV)
-    d = eik.adjoint(F, phi, P.h, P.sources, torch.from_numpy(g.astype(np.float32)).to(DEV))
-    d = d.cpu().numpy().astype(np.float64)
-    do = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, ref, g)
-    assert np.linalg.norm(d - do) <= 2e-2 * np.linalg.norm(do)
-    # Euler identity on the GPU result: sum F dL/dF = -sum_r phi_r
-    L = float(got.flat[P.receivers].sum())
-    assert float((P.F.astype(np.float64) * d).sum()) == pytest.approx(-L, rel=1e-4)
-
-
 def test_batch_256_sampled():
     """The batch recipe at full size (256 grids, sides 128..2048): forward and
-    adjoint of the whole batch, eight seeded grids checked against the
-    oracle (float32 gate for phi; adjoint on the GPU's phi, relative L2)."""
+    adjoint of the whole batch; eight seeded grids checked against the oracle
+    (float32 gates above for phi; the adjoint node by node against the
+    oracle's reverse sweep on the GPU's phi, within the derived float32
+    bound)."""
     Ps = W.batch_2d(256)
     print(f"[case] batch 256, {sum(P.F.size for P in Ps)} nodes", flush=True)
     shapes = [P.F.shape for P in Ps]
@@ -86,12 +87,13 @@ def test_batch_256_sampled():
     r = np.random.default_rng(W.BASE_SEED)
     for i in sorted(int(v) for v in r.choice(len(Ps), size=8, replace=False)):
         P = Ps[i]
-        got = phis[offs[i]:offs[i + 1]].reshape(P.F.shape).astype(np.float64)
+        got = phis[offs[i]:offs[i + 1]].reshape(P.F.shape)
         ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
-        err = np.max(np.abs(got - ref)) / ref.max()
-        print(f"[err] instance {i} {P.F.shape}: {err:.2e}", flush=True)
+        err = np.max(np.abs(got.astype(np.float64) - ref)) / ref.max()
+        ulps = fixed_point_ulps(P.F, P.h, got, P.sources)
+        print(f"[err] instance {i} {P.F.shape}: {err:.2e} of max phi, fixed point {ulps.max():.2f} ulp", flush=True)
         assert err <= 1e-5
+        assert ulps.max() <= MAX_ULPS
         gi = g[offs[i]:offs[i + 1]].reshape(P.F.shape)
-        dref = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, got, gi)
-        dg = ds[offs[i]:offs[i + 1]].reshape(P.F.shape).astype(np.float64)
-        assert np.linalg.norm(dg - dref) <= 2e-2 * np.linalg.norm(dref)
+        dg = ds[offs[i]:offs[i + 1]].reshape(P.F.shape)
+        check_fp32_adjoint(dg, P.F, P.h, P.sources, got, gi, label=f" instance {i}")

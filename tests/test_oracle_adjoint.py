@@ -85,3 +85,38 @@ def test_adjoint_matches_finite_differences_2d():
 
 def test_adjoint_matches_finite_differences_3d():
     _fd_check(W.layered_3d(10, dtype=np.float64, n_receivers=6), 30, 2)
+
+
+def test_adjoint_state_1d_closed_form():
+    """On a strip every node depends on its predecessor alone with weight 1,
+    so the adjoint state is lambda_j = g_j + sum of g over the nodes further
+    from the source (and the source collects everything on its sides)."""
+    r = np.random.default_rng(8)
+    n = 30
+    F = np.exp(r.uniform(-1, 1, size=(1, n)))
+    s = 11
+    phi = oracle.fmm(F, 0.5, [s])
+    g = np.zeros_like(F)
+    g[0, r.choice(n, size=9, replace=False)] = r.uniform(-2, 2, size=9)
+    _, lam = oracle.adjoint(F, 0.5, [s], phi, g, return_lambda=True)
+    want = np.empty(n)
+    for j in range(n):
+        want[j] = g[0, j:].sum() if j > s else g[0, :j + 1].sum() if j < s else g[0].sum()
+    np.testing.assert_allclose(lam[0], want, rtol=0, atol=1e-13)
+
+
+def test_adjoint_state_linearity_and_gradient():
+    """dL/dF = D lambda with lambda linear in dL/dphi: the adjoint of g1 + 2 g2
+    is the sum of the two, and dL/dF / lambda is the same per node for both."""
+    P = W.lognormal_2d(24, dtype=np.float64)
+    phi = oracle.fmm(P.F, P.h, P.sources)
+    r = np.random.default_rng(4)
+    g1, g2 = r.normal(size=phi.shape), r.normal(size=phi.shape)
+    d1, l1 = oracle.adjoint(P.F, P.h, P.sources, phi, g1, return_lambda=True)
+    d2, l2 = oracle.adjoint(P.F, P.h, P.sources, phi, g2, return_lambda=True)
+    d3, l3 = oracle.adjoint(P.F, P.h, P.sources, phi, g1 + 2 * g2, return_lambda=True)
+    np.testing.assert_allclose(l3, l1 + 2 * l2, rtol=1e-12, atol=1e-12 * np.abs(l3).max())
+    np.testing.assert_allclose(d3, d1 + 2 * d2, rtol=1e-12, atol=1e-12 * np.abs(d3).max())
+    m = np.abs(l1) > 1e-6
+    m.flat[P.sources] = False
+    np.testing.assert_allclose(d1[m] / l1[m], d2[m] / l2[m], rtol=1e-9)
