@@ -273,9 +273,10 @@ typedef struct {
  *   report       host, nullable: up to report_cap timed candidates;
  *                *n_report (nullable) receives the count written
  * The choice is cached per (ndim, dtype, log2 of N, per-axis spacing or
- * not) for the life of the process: a later call for the same class times
- * nothing and reports 0
- * entries.  Errors as eik_solve.
+ * not, EIK_FLAG_SKIP_REMEDY and EIK_FLAG_FIFO_REMEDY) for the life of the
+ * process: a later call for the same class times nothing and reports 0
+ * entries.  The arguments are checked as eik_solve checks them before the
+ * cache is consulted; errors as eik_solve.
  */
 eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
                     int64_t n_sources, double eps, void* phi_scratch, eik_options* opt,

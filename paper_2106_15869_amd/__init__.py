@@ -526,14 +526,15 @@ def adjoint_batch(F, phi, shapes, h, sources, dL_dphi, *, out=None, workspace=No
 
 
 def tune(F, h: Optional[float], sources, eps: float = 0.0, *, stream=None, workspace=None,
-         spacing: Optional[Sequence[float]] = None):
+         spacing: Optional[Sequence[float]] = None, fifo: bool = False):
     """Time the tile-variant candidates on this problem (eik_tune) and return
     {"tile": (z, y, x), "inner_iters": k, "candidates": [...]} -- pass tile and
     inner_iters to solve().  Cached per (ndim, dtype, log2 N, per-axis spacing
-    or not) for the process; a cached answer reports no candidates."""
+    or not, remedy schedule) for the process; a cached answer reports no
+    candidates.  fifo: tune the first-in first-out remedy schedule."""
     torch = _torch()
     _check_device_tensor(F, "F")
-    opt = make_options(_dtype_code(F), spacing=spacing)
+    opt = make_options(_dtype_code(F), spacing=spacing, fifo=fifo)
     h = 1.0 if h is None and spacing is not None else h
     s = stream if stream is not None else torch.cuda.current_stream(F.device)
     opt.stream = s.cuda_stream

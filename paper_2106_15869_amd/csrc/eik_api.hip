@@ -61,10 +61,26 @@ static eik_options resolve(const eik_options* opt) {
     return o;
 }
 
+// The option enums come from C callers, for whom any int is a value: they
+// are read as integers until checked (loading an out-of-range value as the
+// enum type is undefined in C++).
+template <typename E>
+static int raw_enum(const E& e) {
+    static_assert(sizeof(E) == sizeof(int), "C enums are int-sized here");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+static bool known_dtype(const eik_options& o) {
+    const int d = raw_enum(o.dtype);
+    return d == EIK_FLOAT32 || d == EIK_FLOAT64;
+}
+
 static eik_status check_options(const eik_options& o) {
-    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64)
-        return fail(EIK_ERR_INVALID_ARGUMENT, "unknown dtype");
-    if (o.variant != EIK_VARIANT_NODE_LIST && o.variant != EIK_VARIANT_TILE && o.variant != EIK_VARIANT_FIM)
+    if (!known_dtype(o)) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown dtype");
+    const int v = raw_enum(o.variant);
+    if (v != EIK_VARIANT_NODE_LIST && v != EIK_VARIANT_TILE && v != EIK_VARIANT_FIM)
         return fail(EIK_ERR_INVALID_ARGUMENT, "unknown variant");
     if (o.variant == EIK_VARIANT_FIM && (o.flags & EIK_FLAG_SKIP_REMEDY))
         return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_VARIANT_FIM has no remedy step to skip");
@@ -342,22 +358,41 @@ EIK_API size_t eik_workspace_size(int32_t ndim, const int64_t* dims, const eik_o
     return workspace_bytes(P, o);
 }
 
-EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
-                             const int64_t* sources, int64_t n_sources, double eps, void* phi_out,
-                             const eik_options* opt) {
-    g_last_error.clear();
-    Problem P;
+namespace eik {
+
+// Every check eik_solve makes before device work (host only).
+static eik_status check_solve(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                              int64_t n_sources, double eps, const void* phi_out, const eik_options& o,
+                              Problem& P, bool& aniso) {
     eik_status rc = check_shape(ndim, dims, P);
     if (rc) return rc;
-    eik_options o = resolve(opt);
     if ((rc = check_options(o))) return rc;
     if (!F || !phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "F and phi_out must be non-NULL");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(EIK_ERR_INVALID_ARGUMENT, "eps must be finite and >= 0");
     if ((rc = check_sources(P, sources, n_sources, o.source_values))) return rc;
     if (F == phi_out) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_out must not alias F");
+    return check_spacing(o, ndim, aniso);
+}
+
+eik_status validate_solve(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                          int64_t n_sources, double eps, const void* phi_out, const eik_options& o) {
+    Problem P;
     bool aniso = false;
-    if ((rc = check_spacing(o, ndim, aniso))) return rc;
+    return check_solve(F, ndim, dims, h, sources, n_sources, eps, phi_out, o, P, aniso);
+}
+
+}  // namespace eik
+
+EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
+                             const int64_t* sources, int64_t n_sources, double eps, void* phi_out,
+                             const eik_options* opt) {
+    g_last_error.clear();
+    Problem P;
+    eik_options o = resolve(opt);
+    bool aniso = false;
+    eik_status rc = check_solve(F, ndim, dims, h, sources, n_sources, eps, phi_out, o, P, aniso);
+    if (rc) return rc;
 
     const size_t need = workspace_bytes(P, o);
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -418,7 +453,7 @@ EIK_API size_t eik_adjoint_workspace_size(int32_t ndim, const int64_t* dims, con
     Problem P;
     if (check_shape(ndim, dims, P) != EIK_OK) return 0;
     eik_options o = resolve(opt);
-    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64) return 0;
+    if (!known_dtype(o)) return 0;
     return adjoint_workspace_bytes(single_batch(P, o, pick_tile(P.g.nd, o), {}, 1.0), elem_size(o.dtype));
 }
 
@@ -576,7 +611,7 @@ EIK_API eik_status eik_solve_batch(const void* F, int32_t ndim, const eik_instan
 EIK_API size_t eik_adjoint_batch_workspace_size(int32_t ndim, const eik_instance* inst, int32_t n_inst,
                                                 const eik_options* opt) {
     eik_options o = resolve(opt);
-    if (o.dtype != EIK_FLOAT32 && o.dtype != EIK_FLOAT64) return 0;
+    if (!known_dtype(o)) return 0;
     Batch b;
     if (make_batch(ndim, inst, n_inst, nullptr, nullptr, o, b) != EIK_OK) return 0;
     return adjoint_workspace_bytes(b, elem_size(o.dtype));
@@ -634,7 +669,7 @@ EIK_API eik_status eik_async_status(const void* workspace, void* stream) {
 }
 
 EIK_API const char* eik_status_string(eik_status s) {
-    switch (s) {
+    switch (raw_enum(s)) {
         case EIK_OK: return "EIK_OK";
         case EIK_ERR_INVALID_ARGUMENT: return "EIK_ERR_INVALID_ARGUMENT";
         case EIK_ERR_NO_CONVERGENCE: return "EIK_ERR_NO_CONVERGENCE";

@@ -29,6 +29,10 @@ inline eik_status fail(eik_status s, const std::string& msg) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Every argument check of eik_solve (no device work; sets the last error).
+eik_status validate_solve(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                          int64_t n_sources, double eps, const void* phi_out, const eik_options& o);
+
 // Pinned host words for counter read-back (one set per host thread).
 struct HostSlots {
     static constexpr int kWords = 8192;  // two slots of segment lengths

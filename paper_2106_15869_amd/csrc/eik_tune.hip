@@ -1,7 +1,7 @@
 // eik_tune: per-problem choice of the tile shape and inner-iteration cap of
 // the tile variant, by timing candidates with HIP events on the caller's
 // stream.  Choices are cached per (ndim, dtype, log2 N, per-axis spacing
-// or not) for the process.
+// or not, remedy schedule flags) for the process.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,15 +25,20 @@ struct Choice {
 };
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, Choice>& tune_cache() {
-    static std::map<std::tuple<int, int, int, int>, Choice> m;
+using TuneKey = std::tuple<int, int, int, int, unsigned>;
+std::map<TuneKey, Choice>& tune_cache() {
+    static std::map<TuneKey, Choice> m;
     return m;
 }
+
+// Flags that change what a tile solve does (and so which shape is fastest).
+constexpr uint32_t kScheduleFlags = EIK_FLAG_SKIP_REMEDY | EIK_FLAG_FIFO_REMEDY;
 
 // A zero tile is the library default: in 2D that runs the update step on
 // 32 x 32 tiles and detection/remedy on 16 x 16, a pairing no explicit shape
 // gives.  Per-axis spacing (Eq 5) is supported on the default shapes only
-// (16 x 16 in 2D, 8^3 in 3D), so only those are timed then.
+// (16 x 16 in 2D, 8^3 in 3D), so only those are timed then; the zero tile is
+// then the same configuration as the explicit default and is left out.
 std::vector<Choice> candidates(int nd, bool aniso) {
     std::vector<Choice> all;
     if (nd == 2)
@@ -47,7 +52,7 @@ std::vector<Choice> candidates(int nd, bool aniso) {
         const bool zero = c.tile[0] == 0 && c.tile[1] == 0 && c.tile[2] == 0;
         const bool def = nd == 2 ? (c.tile[1] == 16 && c.tile[2] == 16)
                                  : (c.tile[0] == 8 && c.tile[1] == 8 && c.tile[2] == 8);
-        if (zero || def) out.push_back(c);
+        if (def && !zero) out.push_back(c);
     }
     return out;
 }
@@ -80,17 +85,26 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     if (n_report) *n_report = 0;
     if (!opt) return fail(EIK_ERR_INVALID_ARGUMENT, "opt is NULL (it receives the choice)");
     if (!phi_scratch) return fail(EIK_ERR_INVALID_ARGUMENT, "phi_scratch is NULL");
-    if ((ndim != 2 && ndim != 3) || !dims) return fail(EIK_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
     if (opt->flags & (EIK_FLAG_ASYNC | EIK_FLAG_PROFILE))
         return fail(EIK_ERR_INVALID_ARGUMENT, "eik_tune runs synchronous, unprofiled solves");
+    {
+        // the candidates' solves check the arguments again; checking here
+        // first means a cached choice is never returned for a call that a
+        // solve would reject
+        eik_options v = *opt;
+        v.variant = EIK_VARIANT_TILE;
+        std::memset(v.tile, 0, sizeof(v.tile));
+        v.inner_iters = 0;
+        const eik_status rc = validate_solve(F, ndim, dims, h, sources, n_sources, eps, phi_scratch, v);
+        if (rc != EIK_OK) return rc;
+    }
     int64_t n = 1;
-    for (int k = 0; k < ndim; ++k) n *= dims[k] > 0 ? dims[k] : 0;
-    if (n < 1) return fail(EIK_ERR_INVALID_ARGUMENT, "every dim must be >= 1");
+    for (int k = 0; k < ndim; ++k) n *= dims[k];
     bool aniso = false;
     for (int k = 0; k < 3; ++k) aniso |= opt->spacing[k] != 0.0;
-    const auto key = std::make_tuple(static_cast<int>(ndim), static_cast<int>(opt->dtype),
-                                     static_cast<int>(std::floor(std::log2(static_cast<double>(n)))),
-                                     static_cast<int>(aniso));
+    const TuneKey key = std::make_tuple(static_cast<int>(ndim), static_cast<int>(opt->dtype),
+                                        static_cast<int>(std::floor(std::log2(static_cast<double>(n)))),
+                                        static_cast<int>(aniso), opt->flags & kScheduleFlags);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = tune_cache().find(key);

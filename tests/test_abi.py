@@ -255,6 +255,15 @@ def test_tune_validation(lib):
     o = eik.make_options(eik.EIK_FLOAT32, "tile")
     assert lib.eik_tune(0x1000, 2, d.ctypes.data, 1.0, s.ctypes.data, 1, 0.0, None, ctypes.byref(o), None, 0,
                         None) == eik.EIK_ERR_INVALID_ARGUMENT
+    # the solve's own checks run before the cache is consulted or any device
+    # work: a source out of range, phi aliasing F, a bad h or eps
+    bad = np.asarray([256], dtype=np.int64)
+    for args, why in [((0x1000, bad, 1.0, 0.0, 0x2000), "range"), ((0x1000, s, 1.0, 0.0, 0x1000), "alias"),
+                      ((0x1000, s, -1.0, 0.0, 0x2000), "h must"), ((0x1000, s, 1.0, -1.0, 0x2000), "eps")]:
+        F, src, h, eps, scratch = args
+        assert lib.eik_tune(F, 2, d.ctypes.data, h, src.ctypes.data, 1, eps, scratch, ctypes.byref(o), None, 0,
+                            None) == eik.EIK_ERR_INVALID_ARGUMENT, why
+        assert why in lib.eik_last_error().decode()
 
 
 @pytest.mark.parametrize("sp,ok", [((0.5, 2.0, 0.0), True), ((0.5, -1.0, 0.0), False), ((0.5, 0.0, 0.0), False),

@@ -98,11 +98,16 @@ def test_tune_with_spacing(case):
     t = eik.tune(Fd, None, src, spacing=sp)
     default = (1, 16, 16) if F.ndim == 2 else (8, 8, 8)
     assert t["candidates"], "first call for this class times candidates"
-    assert all(c["tile"] in {(0, 0, 0), default} for c in t["candidates"])
     got = eik.solve(Fd, None, src, spacing=sp, tile=t["tile"], inner_iters=t["inner_iters"]).cpu().numpy()
     ref = oracle.fmm(F.astype(np.float32).astype(np.float64), 1.0, src, spacing=sp)
     fin = np.isfinite(ref)
     assert np.array_equal(fin, np.isfinite(got))
     assert np.max(np.abs(got[fin] - ref[fin])) <= TOL[np.float32] * ref[fin].max()
-    iso = eik.tune(Fd, 1.0, src)
+    # the isotropic problem of the same size class has its own cache entry
+    # (tuned here for the first-in first-out remedy, a class no other test
+    # tunes, so that the timing is not served from an earlier test's entry)
+    iso = eik.tune(Fd, 1.0, src, fifo=True)
     assert iso["candidates"] and any(c["tile"] not in {(0, 0, 0), default} for c in iso["candidates"])
+    # with spacing the zero tile (the same configuration as the default
+    # shapes then) is not timed twice
+    assert all(c["tile"] == default for c in t["candidates"])
