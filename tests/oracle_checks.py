@@ -35,6 +35,21 @@ float32 rounding of the GPU's arithmetic.  With u = 2^-24:
 Hence |dL/dF_gpu - dL/dF_oracle| <= u |D| ((7 + 2 ND) nu + 12 labs) per node,
 computed here with two more oracle adjoint solves (to first order in u; the
 oracle's own float64 rounding is 2^29 times smaller).
+
+The relative model holds only inside float32's normal range.  Below 2^-126 a
+rounded result carries an absolute error of up to 2^-126 (flushed to zero) or
+half a subnormal step (gradual underflow), whatever its size; gradients of
+cells far upwind of every receiver fall there (2D lognormal batch grids reach
+1e-46).  So every rounding also adds at most tau = 2^-126 absolute: at most
+2 ND + 2 of them per lambda_j, carried like the relative terms, i.e.
+(2 ND + 2) tau nu1_j with nu1 = 1 + M^T nu1 (the adjoint of the all-ones
+loss gradient), and one more for the final product, which gives
+
+    |dL/dF_gpu - dL/dF_oracle| <= u |D| ((7 + 2 ND) nu + 12 labs)
+                                  + tau (1 + (2 ND + 2) |D| nu1).
+
+The floor is below 1e-30 for every grid here, far under any normal-range
+value's relative term.
 """
 
 from __future__ import annotations
@@ -44,6 +59,7 @@ import numpy as np
 import oracle
 
 U32 = 2.0 ** -24
+TINY32 = 2.0 ** -126   # smallest normal float32: the absolute floor of one rounding
 
 
 def fixed_point_ulps(F, h, phi, sources) -> np.ndarray:
@@ -75,7 +91,9 @@ def fp32_adjoint_bound(F, h, sources, phi, g, spacing=None) -> np.ndarray:
     ga = np.abs(np.asarray(g, dtype=np.float64))
     d_abs, labs = oracle.adjoint(F64, h, sources, p, ga, spacing=spacing, return_lambda=True)
     d_nu = oracle.adjoint(F64, h, sources, p, labs, spacing=spacing)
-    return U32 * ((7 + 2 * nd) * np.abs(d_nu) + 12.0 * np.abs(d_abs))
+    d_one = oracle.adjoint(F64, h, sources, p, np.ones_like(p), spacing=spacing)
+    return (U32 * ((7 + 2 * nd) * np.abs(d_nu) + 12.0 * np.abs(d_abs))
+            + TINY32 * (1.0 + (2 * nd + 2) * np.abs(d_one)))
 
 
 def check_fp32_adjoint(got, F, h, sources, phi, g, spacing=None, label=""):

@@ -119,3 +119,22 @@ def test_fixed_point_ulps_of_a_float32_fixed_point():
     k = np.flatnonzero(np.isfinite(moved.ravel()) & (moved.ravel() > 0.5 * np.nanmax(moved)))[0]
     moved.flat[k] = np.float32(moved.flat[k]) + 16 * np.spacing(np.float32(moved.flat[k]))
     assert fixed_point_ulps(P.F, P.h, moved, P.sources).max() >= 8.0
+
+
+def test_fp32_adjoint_bound_covers_underflow():
+    """A loss gradient scaled into float32's subnormal range: the float32
+    adjoint then rounds to multiples of 2^-149, an absolute error the relative
+    part of the bound cannot cover; the underflow floor does, and stays far
+    below any normal-range gradient."""
+    P = W.lognormal_2d(24, seed=5)
+    phi, g = _case(P, 3)
+    g = g * 2.0 ** -135
+    Fq = P.F.astype(np.float32).astype(np.float64)
+    got = _adjoint_f32(P.F, P.h, P.sources, phi, g)
+    want = oracle.adjoint(Fq, P.h, P.sources, phi.astype(np.float64), g)
+    bound = fp32_adjoint_bound(Fq, P.h, P.sources, phi, g)
+    err = np.abs(got - want)
+    assert np.all(err <= bound + 1e-300)
+    relative_only = U32 * 100.0 * np.abs(want)
+    assert np.any(err > relative_only), "expected subnormal rounding beyond any relative bound"
+    assert bound.max() <= 1e-30
