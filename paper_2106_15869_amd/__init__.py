@@ -12,6 +12,8 @@ Functions mirror the C entry points:
 * ``eik_adjoint``      dL/dF at a converged solution.
 * ``eik_solve_batch`` / ``eik_adjoint_batch``  the same for many grids at once.
 * ``eik_async_status`` whether asynchronous (graph-captured) work converged.
+* ``eik_solve_noalloc`` ``eik_solve`` on the library's static device scratch,
+  allocating nothing (for callers that cannot allocate).
 * ``eik_workspace_size``, ``eik_status_string``, ``eik_abi_version``.
 
 ``solve`` / ``apply_local`` / ``adjoint`` / ``solve_batch`` / ``adjoint_batch``
@@ -42,7 +44,7 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 5
+EIK_ABI_VERSION = 6
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
@@ -56,7 +58,7 @@ VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
 EXPORTS = ("eik_default_options", "eik_workspace_size", "eik_solve", "eik_apply_local",
            "eik_adjoint", "eik_adjoint_workspace_size", "eik_status_string", "eik_last_error",
            "eik_abi_version", "eik_solve_batch", "eik_batch_workspace_size", "eik_adjoint_batch",
-           "eik_adjoint_batch_workspace_size", "eik_tune", "eik_async_status")
+           "eik_adjoint_batch_workspace_size", "eik_tune", "eik_async_status", "eik_solve_noalloc")
 
 
 KERNEL_KINDS = ("update", "detect", "remedy", "adjoint", "other")
@@ -163,6 +165,8 @@ def _load():
     lib.eik_adjoint_batch_workspace_size.argtypes = [i32, IP, i32, OP]
     lib.eik_async_status.restype = ctypes.c_int
     lib.eik_async_status.argtypes = [P, P]
+    lib.eik_solve_noalloc.restype = ctypes.c_int
+    lib.eik_solve_noalloc.argtypes = [P, i32, P, d, P, i64, d, P, OP]
     if lib.eik_abi_version() != EIK_ABI_VERSION:
         raise ImportError(f"{LIB_PATH} has ABI version {lib.eik_abi_version()}, this binding expects "
                           f"{EIK_ABI_VERSION}: rebuild it with `python -m paper_2106_15869_amd.build`")
@@ -322,6 +326,44 @@ def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[st
     with torch.cuda.device(F.device):
         rc = _load().eik_solve(F.data_ptr(), F.dim(), _np_ptr(dims), float(h), _np_ptr(src),
                                len(src), float(eps), phi.data_ptr(), ctypes.byref(opt))
+    _check(rc)
+    return (phi, st.to_dict()) if stats else phi
+
+
+def solve_noalloc(F, h: Optional[float], sources, eps: float = 0.0, *, out=None,
+                  variant: Union[str, int] = "tile", source_values=None, deterministic: bool = False,
+                  skip_remedy: bool = False, tile: Optional[Sequence[int]] = None, inner_iters: int = 0,
+                  max_iters: int = 0, stats: bool = False, stream=None, fifo: bool = False,
+                  spacing: Optional[Sequence[float]] = None):
+    """eik_solve_noalloc: solve() on the library's static device scratch (no
+    workspace argument; the library allocates nothing).  Synchronous only.
+    Pass `out` to keep the call free of allocations on this side too."""
+    torch = _torch()
+    _check_device_tensor(F, "F")
+    if F.dim() not in (2, 3):
+        raise ValueError("F must be 2D or 3D")
+    opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
+                       skip_remedy, fifo=fifo, spacing=spacing)
+    h = 1.0 if h is None and spacing is not None else h
+    dims = _dims(F.shape)
+    src = _sources_array(sources, F.shape)
+    vals = None
+    if source_values is not None:
+        vals = np.ascontiguousarray(np.asarray(source_values, dtype=np.float64).ravel())
+        if vals.shape != src.shape:
+            raise ValueError("source_values must match sources")
+        opt.source_values = vals.ctypes.data
+    phi = out if out is not None else torch.empty_like(F)
+    _check_device_tensor(phi, "out")
+    if phi.shape != F.shape or phi.dtype != F.dtype:
+        raise ValueError("out must match F in shape and dtype")
+    st = EikStats()
+    opt.stats = ctypes.pointer(st)
+    s = stream if stream is not None else torch.cuda.current_stream(F.device)
+    opt.stream = s.cuda_stream
+    with torch.cuda.device(F.device):
+        rc = _load().eik_solve_noalloc(F.data_ptr(), F.dim(), _np_ptr(dims), float(h), _np_ptr(src),
+                                       len(src), float(eps), phi.data_ptr(), ctypes.byref(opt))
     _check(rc)
     return (phi, st.to_dict()) if stats else phi
 

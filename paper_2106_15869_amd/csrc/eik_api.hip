@@ -233,6 +233,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>&
     const bool det = (o.flags & EIK_FLAG_DETERMINISTIC) != 0;
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
     const bool fim = o.variant == EIK_VARIANT_FIM;
+    const bool pageable = (o.flags & kFlagPageable) != 0;
     NodeWs w = node_layout(ws, P.n, sizeof(T), det, fim);
     const int64_t cap = o.max_iters > 0 ? o.max_iters : 4 * P.n + 64;
     int64_t launched = 0;
@@ -293,7 +294,7 @@ static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>&
                            : launch_step2<T>(P.g, iter_args(t, t == 0), hT, eT, det, s);
             });
         },
-        counts, kNodeSegs, cap, async, s, &n2, w.ctl);
+        counts, kNodeSegs, cap, async, s, &n2, w.ctl, pageable);
     launched += (fim ? 2 : per_iter) * n2;
     if (rc == EIK_OK && !fim && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // STEP 3a: whole-grid check into list 0
@@ -306,28 +307,27 @@ static eik_status solve_nodelist(const Problem& P, const T* F, const Spacing<T>&
                 return timed(prof, EIK_KERNEL_REMEDY,
                              [&] { return launch_remedy<T>(P.g, iter_args(t, t == 0), hT, eT, det, s); });
             },
-            counts, kNodeSegs, cap, async, s, &n3, w.ctl);
+            counts, kNodeSegs, cap, async, s, &n3, w.ctl, pageable);
         launched += per_iter * n3;
     }
     if (async) return rc;
-    HostSlots& hs = host_slots();
-    HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hs.blk, w.blkstat, blk_bytes, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
+    Results res;
+    const eik_status rr = read_results(w.ctl, w.blkstat, kNodeSegs, pageable, s, res);
+    if (rr != EIK_OK) return rr;
+    if (res.ctl.err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
     if (st) {
         *st = eik_stats{};
-        st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
-        st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
-        st->evals_step2 = static_cast<int64_t>(hs.ctl->evals2);
+        st->step2_iters = static_cast<int64_t>(res.ctl.iters2);
+        st->step3_iters = static_cast<int64_t>(res.ctl.iters3);
+        st->evals_step2 = static_cast<int64_t>(res.ctl.evals2);
         st->evals_detect = (fim || (o.flags & EIK_FLAG_SKIP_REMEDY)) ? 0 : P.n - static_cast<int64_t>(src.size());
-        st->evals_check = static_cast<int64_t>(blk_sum(hs.blk, SF_CHECK, kNodeSegs));
-        st->evals_remedy = static_cast<int64_t>(hs.ctl->evals_rem);
-        st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
-        st->max_active = static_cast<int64_t>(hs.ctl->max_active);
+        st->evals_check = static_cast<int64_t>(res.sum[SF_CHECK]);
+        st->evals_remedy = static_cast<int64_t>(res.ctl.evals_rem);
+        st->remedy_initial = static_cast<int64_t>(res.ctl.remedy_init);
+        st->max_active = static_cast<int64_t>(res.ctl.max_active);
         st->launches = launched;
-        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, kNodeSegs));
-        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, kNodeSegs));
+        st->written_step2 = static_cast<int64_t>(res.sum[SF_WRITTEN2]);
+        st->written_step3 = static_cast<int64_t>(res.sum[SF_WRITTEN3]);
         HIP_TRY(prof.collect(st));
     }
     return rc;
@@ -384,15 +384,17 @@ eik_status validate_solve(const void* F, int32_t ndim, const int64_t* dims, doub
 
 }  // namespace eik
 
-EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
-                             const int64_t* sources, int64_t n_sources, double eps, void* phi_out,
-                             const eik_options* opt) {
-    g_last_error.clear();
+namespace eik {
+
+eik_status solve_entry(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                       int64_t n_sources, double eps, void* phi_out, const eik_options& checked,
+                       uint32_t internal) {
     Problem P;
-    eik_options o = resolve(opt);
+    eik_options o = checked;
     bool aniso = false;
     eik_status rc = check_solve(F, ndim, dims, h, sources, n_sources, eps, phi_out, o, P, aniso);
     if (rc) return rc;
+    o.flags |= internal;
 
     const size_t need = workspace_bytes(P, o);
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -420,6 +422,15 @@ EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, d
                                       static_cast<double*>(phi_out), o, ws, s, o.stats);
     return solve_nodelist<float>(P, static_cast<const float*>(F), make_spacing<float>(h, o, aniso), eps, src,
                                  static_cast<float*>(phi_out), o, ws, s, o.stats);
+}
+
+}  // namespace eik
+
+EIK_API eik_status eik_solve(const void* F, int32_t ndim, const int64_t* dims, double h,
+                             const int64_t* sources, int64_t n_sources, double eps, void* phi_out,
+                             const eik_options* opt) {
+    g_last_error.clear();
+    return solve_entry(F, ndim, dims, h, sources, n_sources, eps, phi_out, resolve(opt), 0u);
 }
 
 EIK_API eik_status eik_apply_local(const void* F, const void* phi, int32_t ndim,

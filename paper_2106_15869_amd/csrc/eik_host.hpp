@@ -33,6 +33,12 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 eik_status validate_solve(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
                           int64_t n_sources, double eps, const void* phi_out, const eik_options& o);
 
+// eik_solve's checks, workspace and schedule on options with the defaults
+// filled in; `internal` option bits (kFlagPageable) are added after the
+// checks, which reject them from callers.
+eik_status solve_entry(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
+                       int64_t n_sources, double eps, void* phi_out, const eik_options& o, uint32_t internal);
+
 // Pinned host words for counter read-back (one set per host thread).
 struct HostSlots {
     static constexpr int kWords = 8192;  // two slots of segment lengths
@@ -146,18 +152,40 @@ inline unsigned long long blk_sum(const unsigned long long* blk, int field, int 
 // steps are enqueued, launches after convergence finding empty lists, and a
 // last kernel records in ctl->open_lists whether work was left over (read
 // back later by eik_async_status).
+// With `pageable` the lengths are copied into a stack buffer after each
+// chunk and the host waits for them before enqueuing the next chunk (no
+// pinned memory, no events; the device idles while the host enqueues).
 template <typename StepFn, typename CountsFn>
 inline eik_status run_loop(StepFn step, CountsFn counts, int nseg, int64_t max_iters, bool async,
-                           hipStream_t s, int64_t* steps, Ctl* ctl) {
+                           hipStream_t s, int64_t* steps, Ctl* ctl, bool pageable = false) {
     if (async) {
         for (int64_t t = 0; t < max_iters; ++t) HIP_TRY(step(t));
         HIP_TRY(launch_loop_status(ctl, counts(max_iters), nseg, s));
         *steps = max_iters;
         return EIK_OK;
     }
+    if (nseg > HostSlots::kWords / 2) return fail(EIK_ERR_UNSUPPORTED, "too many list segments");
+    if (pageable) {
+        int words[HostSlots::kWords / 2];
+        int64_t t = 0;
+        for (;;) {
+            const int64_t end = std::min(max_iters, t + 16);
+            for (; t < end; ++t) HIP_TRY(step(t));
+            HIP_TRY(hipMemcpyAsync(words, counts(t), nseg * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            long long sum = 0;
+            for (int k = 0; k < nseg; ++k) sum += words[k];
+            if (sum == 0) break;
+            if (t >= max_iters) {
+                *steps = t;
+                return fail(EIK_ERR_NO_CONVERGENCE, "iteration cap reached");
+            }
+        }
+        *steps = t;
+        return EIK_OK;
+    }
     HostSlots& hs = host_slots();
     if (!hs.ok) return fail(EIK_ERR_DEVICE, "pinned host buffer allocation failed");
-    if (nseg > HostSlots::kWords / 2) return fail(EIK_ERR_UNSUPPORTED, "too many list segments");
     const int64_t chunk = 8;  // even: list parity repeats
     auto total = [&](int slot) {
         long long sum = 0;
@@ -187,6 +215,34 @@ inline eik_status run_loop(StepFn step, CountsFn counts, int nseg, int64_t max_i
         slot ^= 1;
     }
     *steps = t;
+    return EIK_OK;
+}
+
+// The control block and the statistics totals of a synchronous call, after
+// its last kernel: through the per-thread pinned slots, or (pageable) by
+// summing the statistics on the device and copying the totals into *r.
+struct Results {
+    Ctl ctl;
+    unsigned long long sum[kStatFields];
+};
+
+inline eik_status read_results(const Ctl* dctl, unsigned long long* blkstat, int nblocks, bool pageable,
+                               hipStream_t s, Results& r) {
+    if (pageable) {
+        HIP_TRY(launch_sum_stats(blkstat, nblocks, s));
+        HIP_TRY(hipMemcpyAsync(&r.ctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(r.sum, blkstat, sizeof(r.sum), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return EIK_OK;
+    }
+    HostSlots& hs = host_slots();
+    if (!hs.ok) return fail(EIK_ERR_DEVICE, "pinned host buffer allocation failed");
+    HIP_TRY(hipMemcpyAsync(hs.ctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hs.blk, blkstat, sizeof(unsigned long long) * kStatFields * nblocks,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    r.ctl = *hs.ctl;
+    for (int f = 0; f < kStatFields; ++f) r.sum[f] = blk_sum(hs.blk, f, nblocks);
     return EIK_OK;
 }
 

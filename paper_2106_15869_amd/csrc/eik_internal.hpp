@@ -41,6 +41,12 @@ enum StatField {
 };
 constexpr int kMaxStatBlocks = 2048;
 
+// Internal option bit, added after the caller's options are checked (callers
+// cannot set it): a synchronous call reads its list lengths and results back
+// through pageable host memory instead of the per-thread pinned slots and
+// events, so that it allocates nothing (the no-allocation entry point).
+constexpr uint32_t kFlagPageable = 1u << 31;
+
 constexpr int kMaxSrcBatch = 64;
 
 template <typename T>
@@ -156,5 +162,8 @@ hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s);
 // length words of the list the next launch would drain and records in
 // ctl->open_lists whether it is non-empty.
 hipError_t launch_loop_status(Ctl* ctl, const int* counts, int nseg, hipStream_t s);
+// Sums each statistics field of a [kStatFields][nblocks] array into its
+// first kStatFields words.
+hipError_t launch_sum_stats(unsigned long long* blkstat, int nblocks, hipStream_t s);
 
 }  // namespace eik

@@ -590,6 +590,27 @@ __global__ __launch_bounds__(kBlock) void k_loop_status(Ctl* ctl, const int* cou
     if (__syncthreads_or(any) && threadIdx.x == 0) ctl->open_lists = 1;
 }
 
+// Totals of the per-workgroup statistics: field f summed over its nblocks
+// columns lands in word f of the array (one block; every column is read
+// before any total is written), so a read-back moves kStatFields words.
+__global__ __launch_bounds__(kBlock) void k_sum_stats(unsigned long long* blk, int nblocks) {
+    __shared__ unsigned long long part[kBlock];
+    __shared__ unsigned long long tot[kStatFields];
+    for (int f = 0; f < kStatFields; ++f) {
+        unsigned long long v = 0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) v += blk[f * nblocks + b];
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[f] = part[0];
+        __syncthreads();
+    }
+    if (threadIdx.x < kStatFields) blk[threadIdx.x] = tot[threadIdx.x];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -724,6 +745,11 @@ hipError_t launch_reset_counters(Ctl* ctl, hipStream_t s) {
 
 hipError_t launch_ctl_init(Ctl* ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_stats(unsigned long long* blkstat, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_stats, dim3(1), dim3(kBlock), 0, s, blkstat, nblocks);
     return hipGetLastError();
 }
 

@@ -866,6 +866,7 @@ template <typename T>
 eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_options& o, char* ws,
                       hipStream_t s, eik_stats* st) {
     const bool async = (o.flags & EIK_FLAG_ASYNC) != 0;
+    const bool pageable = (o.flags & kFlagPageable) != 0;
     const TileCfg c = b.cfg;
     TileOps<T> k;
     if (!select_ops<T>(b.nd, c, b.inst[0].aniso != 0, k))
@@ -965,7 +966,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         [&](int64_t t) {
             return timed(prof, EIK_KERNEL_UPDATE, [&] { return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, s); });
         },
-        counts, kSub * kPad, cap, async, s, &n2, w.ctl);
+        counts, kSub * kPad, cap, async, s, &n2, w.ctl, pageable);
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
@@ -995,31 +996,30 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
                 }
                 return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(a, geom, eT, inner, s); });
             },
-            counts, kSub * kPad, cap, async, s, &n3, w.ctl);
+            counts, kSub * kPad, cap, async, s, &n3, w.ctl, pageable);
         launched += (ordered ? 2 : 1) * n3;
     }
     if (async) return rc;
-    HostSlots& hs = host_slots();
-    HIP_TRY(hipMemcpyAsync(hs.ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hs.blk, w.blkstat, blk_bytes, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hs.ctl->err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
+    Results res;
+    const eik_status rr = read_results(w.ctl, w.blkstat, kMaxStatBlocks, pageable, s, res);
+    if (rr != EIK_OK) return rr;
+    if (res.ctl.err & 1) return fail(EIK_ERR_INVALID_ARGUMENT, "F has negative or non-finite values");
     if (st) {
         *st = eik_stats{};
-        st->step2_iters = static_cast<int64_t>(hs.ctl->iters2);
-        st->step3_iters = static_cast<int64_t>(hs.ctl->iters3);
-        st->evals_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS2, kMaxStatBlocks));
+        st->step2_iters = static_cast<int64_t>(res.ctl.iters2);
+        st->step3_iters = static_cast<int64_t>(res.ctl.iters3);
+        st->evals_step2 = static_cast<int64_t>(res.sum[SF_EVALS2]);
         st->evals_detect = (o.flags & EIK_FLAG_SKIP_REMEDY) ? 0 : b.n - static_cast<int64_t>(b.src.size());
-        st->evals_remedy = static_cast<int64_t>(blk_sum(hs.blk, SF_EVALS3, kMaxStatBlocks));
-        st->remedy_initial = static_cast<int64_t>(hs.ctl->remedy_init);
-        st->max_active = static_cast<int64_t>(hs.ctl->max_active);
+        st->evals_remedy = static_cast<int64_t>(res.sum[SF_EVALS3]);
+        st->remedy_initial = static_cast<int64_t>(res.ctl.remedy_init);
+        st->max_active = static_cast<int64_t>(res.ctl.max_active);
         st->launches = launched;
-        st->tile_visits_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS2, kMaxStatBlocks));
-        st->tile_visits_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_VISITS3, kMaxStatBlocks));
-        st->inner_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER2, kMaxStatBlocks));
-        st->inner_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_INNER3, kMaxStatBlocks));
-        st->written_step2 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN2, kMaxStatBlocks));
-        st->written_step3 = static_cast<int64_t>(blk_sum(hs.blk, SF_WRITTEN3, kMaxStatBlocks));
+        st->tile_visits_step2 = static_cast<int64_t>(res.sum[SF_VISITS2]);
+        st->tile_visits_step3 = static_cast<int64_t>(res.sum[SF_VISITS3]);
+        st->inner_step2 = static_cast<int64_t>(res.sum[SF_INNER2]);
+        st->inner_step3 = static_cast<int64_t>(res.sum[SF_INNER3]);
+        st->written_step2 = static_cast<int64_t>(res.sum[SF_WRITTEN2]);
+        st->written_step3 = static_cast<int64_t>(res.sum[SF_WRITTEN3]);
         HIP_TRY(prof.collect(st));
     }
     return rc;

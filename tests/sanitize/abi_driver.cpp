@@ -221,11 +221,36 @@ static void misc() {
     CHECK(std::strlen(eik_last_error()) > 0, "last error set");
 }
 
+// The no-allocation entry point: everything it refuses before device work.
+static void noalloc_validation() {
+    int64_t big[3] = {512, 512, 512}, d2[2] = {8, 8}, s0 = 0, far = 64;
+    eik_options o = defaults();
+    CHECK(eik_solve_noalloc(kF, 3, big, 1.0, &s0, 1, 0.0, kPhi, &o) == EIK_ERR_OUT_OF_MEMORY, "noalloc size");
+    eik_options ws = defaults();
+    ws.workspace = kG;
+    ws.workspace_bytes = 1 << 20;
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &ws) == EIK_ERR_INVALID_ARGUMENT, "noalloc workspace");
+    eik_options a = defaults();
+    a.flags = EIK_FLAG_ASYNC;
+    a.max_iters = 8;
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &a) == EIK_ERR_UNSUPPORTED, "noalloc async");
+    eik_options p = defaults();
+    p.flags = EIK_FLAG_PROFILE;
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &p) == EIK_ERR_UNSUPPORTED, "noalloc profile");
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &far, 1, 0.0, kPhi, nullptr) == EIK_ERR_INVALID_ARGUMENT,
+          "noalloc source range");
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kF, nullptr) == EIK_ERR_INVALID_ARGUMENT, "noalloc alias");
+    eik_options f = defaults();
+    f.flags = 1u << 31;
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &f) == EIK_ERR_INVALID_ARGUMENT, "noalloc flags");
+}
+
 int main() {
     size_queries();
     solve_validation();
     batch_validation();
     misc();
+    noalloc_validation();
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);
         return 1;

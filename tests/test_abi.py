@@ -297,3 +297,39 @@ def test_async_status_rejects_bad_workspace(lib):
     assert b"NULL" in lib.eik_last_error()
     assert lib.eik_async_status(0x1010, None) == eik.EIK_ERR_INVALID_ARGUMENT
     assert b"aligned" in lib.eik_last_error()
+
+
+def _noalloc_raw(lib, dims, opt=None, F=0x1000, phi=0x2000, sources=(0,)):
+    d = np.asarray(dims, dtype=np.int64)
+    s = np.asarray(sources, dtype=np.int64)
+    return lib.eik_solve_noalloc(F, len(d), d.ctypes.data, 1.0, s.ctypes.data, len(s), 0.0, phi,
+                                 ctypes.byref(opt) if opt is not None else None)
+
+
+def test_noalloc_rejects_before_device_work(lib):
+    """eik_solve_noalloc answers these on the host: a problem whose workspace
+    exceeds the 64 MiB static scratch, a caller workspace, asynchronous or
+    profiled calls, and eik_solve's own argument checks."""
+    big = (512, 512, 512)
+    o = eik.make_options(eik.EIK_FLOAT32, "tile")
+    assert eik.eik_workspace_size(big, o) > 64 << 20
+    assert _noalloc_raw(lib, big, o) == eik.EIK_ERR_OUT_OF_MEMORY
+    assert b"static scratch" in lib.eik_last_error()
+    node = eik.make_options(eik.EIK_FLOAT32, "node")
+    assert eik.eik_workspace_size((2048, 2048), node) > 64 << 20
+    assert _noalloc_raw(lib, (2048, 2048), node) == eik.EIK_ERR_OUT_OF_MEMORY
+    ws = eik.make_options(eik.EIK_FLOAT32, "tile")
+    ws.workspace = 0x10000
+    ws.workspace_bytes = 1 << 20
+    assert _noalloc_raw(lib, (8, 8), ws) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert b"workspace must be NULL" in lib.eik_last_error()
+    a = eik.make_options(eik.EIK_FLOAT32, "tile", async_=True, max_iters=10)
+    assert _noalloc_raw(lib, (8, 8), a) == eik.EIK_ERR_UNSUPPORTED
+    p = eik.make_options(eik.EIK_FLOAT32, "tile", profile=True)
+    assert _noalloc_raw(lib, (8, 8), p) == eik.EIK_ERR_UNSUPPORTED
+    assert _noalloc_raw(lib, (8, 8), sources=(64,)) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert _noalloc_raw(lib, (8, 8), phi=0x1000) == eik.EIK_ERR_INVALID_ARGUMENT
+    assert _noalloc_raw(lib, (8, 8), F=None) == eik.EIK_ERR_INVALID_ARGUMENT
+    bad = eik.make_options(eik.EIK_FLOAT32, "tile")
+    bad.flags = 1 << 31
+    assert _noalloc_raw(lib, (8, 8), bad) == eik.EIK_ERR_INVALID_ARGUMENT
