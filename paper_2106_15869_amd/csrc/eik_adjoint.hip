@@ -200,9 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
     const int len = from_work ? s_wlen[k] : s_len[k];
     constexpr int SY = S::LX, SZ = S::LX * S::LY;
     unsigned long long visits = 0;
-    for (;;) {
+    for (bool first = true;; first = false) {
         if (threadIdx.x == 0) {
-            const int e = atomicAdd(src.fetch + k * kPad, 1);
+            const int e = fetch_index(src, k, first);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
             if (tt >= 0) {

@@ -227,8 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
     const int k = blockIdx.x & (kSub - 1);
     const int len = s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
-    for (;;) {
-        const int t = list_fetch(a.cur, k, len, &s_slot);
+    for (bool first = true;; first = false) {
+        const int t = list_fetch(a.cur, k, len, &s_slot, first);
         if (t < 0) break;
         ++visits;
         const Inst<T> g = inst_of(bg, t);
@@ -510,9 +510,9 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
     const int k = blockIdx.x & (kSub - 1);
     const int len = from_work ? s_wlen[k] : s_len[k];
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
-    for (;;) {
+    for (bool first = true;; first = false) {
         if (threadIdx.x == 0) {
-            const int e = atomicAdd(src.fetch + k * kPad, 1);
+            const int e = fetch_index(src, k, first);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
             if (e < len && from_work) {
