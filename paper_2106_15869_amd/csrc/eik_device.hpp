@@ -50,45 +50,42 @@ __device__ __forceinline__ void decode(const Grid& g, int i, int& x, int& y, int
 // Written relative to the smallest minimum (b_k = a_k - a_1) so that large
 // arrival times do not cancel; an axis joins while the running root still
 // exceeds its minimum.  Returns +inf when nothing upwind is finite or H = +inf.
+// Branch-free: the minima are sorted with a min/max network, the one-, two-
+// and three-sided roots are all formed and the progressive rule selects one
+// (the same value, bit for bit, as evaluating them in turn; a root formed
+// from an infinite minimum is never selected).
 template <typename T, int ND>
 __device__ __forceinline__ T godunov(T a0, T a1, T a2, T H) {
     const T inf = pos_inf<T>();
-    // ascending sort
-    T lo = tmin(a0, a1), hi = a0 < a1 ? a1 : a0;
-    a0 = lo;
-    a1 = hi;
+    const T lo = fmin(a0, a1), hi = fmax(a0, a1);
     if (ND == 3) {
-        T m2 = a2;
-        if (m2 < a1) {
-            a2 = a1;
-            a1 = m2;
-            if (a1 < a0) {
-                T t = a0;
-                a0 = a1;
-                a1 = t;
-            }
-        }
+        const T m = fmin(hi, a2);
+        a2 = fmax(hi, a2);
+        a0 = fmin(lo, m);
+        a1 = fmax(lo, m);
+    } else {
+        a0 = lo;
+        a1 = hi;
     }
-    if (!(H < inf) || !(a0 < inf)) return inf;
-    T phi = a0 + H;
-    if (!(phi > a1)) return phi;
+    const T phi1 = a0 + H;
     T b = a1 - a0;
     T S = b;
     T Q = b * b;
-    T HH = H * H;
+    const T HH = H * H;
     T disc = S * S - T(2) * (Q - HH);
     disc = disc < T(0) ? T(0) : disc;
-    phi = a0 + (S + dev_sqrt(disc)) / T(2);
+    const T phi2 = a0 + (S + dev_sqrt(disc)) / T(2);
+    T phi = phi1 > a1 ? phi2 : phi1;
     if (ND == 3) {
-        if (!(phi > a2)) return phi;
         b = a2 - a0;
         S = S + b;
         Q = Q + b * b;
         disc = S * S - T(3) * (Q - HH);
         disc = disc < T(0) ? T(0) : disc;
-        phi = a0 + (S + dev_sqrt(disc)) / T(3);
+        const T phi3 = a0 + (S + dev_sqrt(disc)) / T(3);
+        phi = phi1 > a1 && phi2 > a2 ? phi3 : phi;
     }
-    return phi;
+    return H < inf && a0 < inf ? phi : inf;
 }
 
 // H_i = h / F_i, +inf for a barrier cell.

@@ -6,6 +6,9 @@ the exact local solve (Eq 4 / Eq 6), node by node, in float32 ulps.
 fp32_adjoint_bound / check_fp32_adjoint: rounding bound of a float32 adjoint,
 node by node.
 
+chain_bound: bound on the distance of a float32 solution from the float64
+fixed point, from the float32 solution's own per-node residual.
+
 The GPU adjoint and the float64 oracle adjoint are compared on the SAME
 solution phi (the GPU's float32 output, upcast exactly).  Both then use the
 same upwind stencil at every node (the stencil is read off phi, the lower
@@ -112,3 +115,31 @@ def check_fp32_adjoint(got, F, h, sources, phi, g, spacing=None, label=""):
           f"max err/bound {ratio:.3e}; nodes over the bound {int(bad.sum())}", flush=True)
     assert not bad.any(), (int(bad.sum()), float(err[bad].max()), float(bound[bad].min()))
     return err.max() / scale, ratio
+
+
+def chain_bound(F, h, sources, phi, source_values=None) -> float:
+    """Bound on max |phi - phi64| (phi64 the float64 fixed point) from the
+    residual of `phi` (float32) under the exact local solve.
+
+    The Godunov update G (Eq 4 / Eq 6) is monotone, G(x + c) = G(x) + c for a
+    constant c added to every input, and G_i depends only on neighbours whose
+    value is below G_i (an input at or above the root does not enter it).  So
+    at node i, with e = phi - phi64 and r_i = |phi_i - G_i(phi)|:
+        e_i <= max(e_k over neighbours k below phi64_i) + r_i,   and
+       -e_i <= max(-e_k over neighbours k below phi_i)  + r_i;
+    a chain of such neighbours ends at a source, and each step drops by at
+    least H_k / sqrt(d) >= h / (F_max sqrt(d)) (the local lower bound
+    a_1 + H / sqrt(d) <= G).  Hence
+        max |e| <= (sqrt(d) F_max max(phi) / h) max r + max |source rounding|.
+    """
+    F64 = np.asarray(F, dtype=np.float64)
+    p = np.asarray(phi)
+    G = oracle.apply_local(F64, h, p.astype(np.float64))
+    m = np.isfinite(p) & (F64 > 0)
+    m.flat[np.asarray(sources, dtype=np.int64)] = False
+    r = float(np.max(np.abs(p[m].astype(np.float64) - G[m]))) if m.any() else 0.0
+    top = float(np.max(p[np.isfinite(p)].astype(np.float64)))
+    steps = np.sqrt(np.ndim(F64)) * float(F64.max()) * top / h
+    vals = np.zeros(len(np.ravel(sources))) if source_values is None else np.asarray(source_values, dtype=np.float64)
+    src = float(np.max(np.abs(vals.astype(np.float32).astype(np.float64) - vals))) if vals.size else 0.0
+    return steps * r + src

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.oracle_checks import U32, fixed_point_ulps, fp32_adjoint_bound
+from tests.oracle_checks import U32, chain_bound, fixed_point_ulps, fp32_adjoint_bound
 
 
 def _adjoint_f32(F, h, sources, phi, g, plant=None):
@@ -138,3 +138,23 @@ def test_fp32_adjoint_bound_covers_underflow():
     relative_only = U32 * 100.0 * np.abs(want)
     assert np.any(err > relative_only), "expected subnormal rounding beyond any relative bound"
     assert bound.max() <= 1e-30
+
+
+@pytest.mark.parametrize("P", [W.paper_example(1, 300), W.paper_example(3, 200), W.lognormal_2d(96, seed=4),
+                               W.maze_3d(24)], ids=lambda P: P.name)
+def test_chain_bound_holds_for_the_float32_emulation(P):
+    """The oracle's float32 emulation of Algorithm 2 (a float32 fixed point)
+    stays within chain_bound of the float64 fixed point; a value lowered by
+    a thousandth of max phi (a wrong but locally consistent node would need
+    its neighbours to follow) shows up as a residual far above it."""
+    phi, _ = oracle.ifim(P.F, P.h, P.sources, dtype=np.float32, values=P.source_values)
+    ref = oracle.fmm(P.F.astype(np.float32).astype(np.float64), P.h, P.sources, values=P.source_values)
+    err = float(np.max(np.abs(phi.astype(np.float64)[np.isfinite(ref)] - ref[np.isfinite(ref)])))
+    b = chain_bound(P.F.astype(np.float32), P.h, P.sources, phi, P.source_values)
+    assert err <= b
+    assert b <= 1e-2 * float(np.max(ref[np.isfinite(ref)]))
+    bad = phi.copy()
+    fin = np.flatnonzero(np.isfinite(bad.ravel()))
+    k = fin[np.argmax(bad.ravel()[fin])]
+    bad.flat[k] = np.float32(bad.flat[k] - 1e-3 * np.max(bad.ravel()[fin]))
+    assert fixed_point_ulps(P.F.astype(np.float32), P.h, bad, P.sources).max() > 100.0
