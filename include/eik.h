@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 6
+#define EIK_ABI_VERSION 7
 
 typedef enum {
     EIK_OK = 0,
@@ -147,6 +147,14 @@ typedef struct {
                                   all zero -> the isotropic h argument; else the
                                   first ndim entries must be finite and > 0 and
                                   replace h (which must still be valid) */
+    int32_t order_min;         /* tile variant, ordered remedy: a remedy launch
+                                  takes at least this many of the queued tiles
+                                  with the lowest keys; 0 = default (1024 in 3D,
+                                  512 in 2D) */
+    int32_t workgroups;        /* tile variant: persistent workgroups per tile
+                                  launch, a multiple of 8 up to 2048; 0 = default
+                                  (1536 in 3D: six resident per CU on 256 CUs;
+                                  2048 in 2D) */
 } eik_options;
 
 /* Fill *opt with the defaults listed above.  Never fails. */
@@ -254,29 +262,36 @@ typedef struct {
     int32_t tile[3];      /* (z, y, x) */
     int32_t inner_iters;  /* inner iterations per tile visit */
     double ms;            /* best device time of a solve (HIP events) */
+    int32_t order_min;    /* as eik_options.order_min (0: default) */
+    int32_t workgroups;   /* as eik_options.workgroups (0: default) */
 } eik_tune_entry;
 
 /*
- * eik_tune -- choose the tile shape and inner-iteration cap of the tile
- * variant for a problem by timing candidate configurations on it (each
- * solved once to warm up, then timed; device time from HIP events on
- * opt->stream).  Not in the paper: its run times depend on the GPU's
- * work-group size, and the tile shape plays that role here.
+ * eik_tune -- choose the schedule of the tile variant for a problem by timing
+ * candidate configurations on it (each solved once to warm up, then the
+ * best of two timed solves; device time from HIP events on opt->stream):
+ * first the tile shape and inner-iteration cap, then, for that shape, the
+ * ordered remedy's per-launch minimum (half, the default and twice the
+ * default; not with EIK_FLAG_FIFO_REMEDY or EIK_FLAG_SKIP_REMEDY) and the
+ * persistent workgroups per launch (1024, 1536, 2048).  Not in the paper: its
+ * run times depend on the GPU's work-group size, and the tile shape and
+ * launch width play that role here.
  *   F, ndim, dims, h, sources, n_sources, eps  as eik_solve
  *   phi_scratch  device, N elements; overwritten by the timed solves
  *   opt          in: dtype, stream, spacing (per-axis spacing times only the
  *                default shapes, the only ones it runs on), workspace (used
- *                when large enough, else the library allocates); out: tile
- *                and inner_iters of the
- *                fastest candidate, variant = EIK_VARIANT_TILE (tile
- *                (0, 0, 0) when the default shapes won)
+ *                when large enough, else the library allocates); out: tile,
+ *                inner_iters, order_min and workgroups of the fastest
+ *                candidate, variant = EIK_VARIANT_TILE (tile (0, 0, 0) when
+ *                the default shapes won; 0 for a default order_min or
+ *                workgroups)
  *   report       host, nullable: up to report_cap timed candidates;
  *                *n_report (nullable) receives the count written
  * The choice is cached per (ndim, dtype, log2 of N, per-axis spacing or
  * not, EIK_FLAG_SKIP_REMEDY and EIK_FLAG_FIFO_REMEDY) for the life of the
- * process: a later call for the same class times nothing and reports 0
- * entries.  The arguments are checked as eik_solve checks them before the
- * cache is consulted; errors as eik_solve.
+ * process, whatever the speed field: a later call for the same class times
+ * nothing and reports 0 entries.  The arguments are checked as eik_solve
+ * checks them before the cache is consulted; errors as eik_solve.
  */
 eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, double h, const int64_t* sources,
                     int64_t n_sources, double eps, void* phi_scratch, eik_options* opt,

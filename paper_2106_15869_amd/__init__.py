@@ -44,7 +44,7 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 6
+EIK_ABI_VERSION = 7
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
@@ -71,7 +71,8 @@ class EikInstance(ctypes.Structure):
 
 class EikTuneEntry(ctypes.Structure):
     """eik_tune_entry: one timed candidate."""
-    _fields_ = [("tile", ctypes.c_int32 * 3), ("inner_iters", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("tile", ctypes.c_int32 * 3), ("inner_iters", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("order_min", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
 
 
 class EikStats(ctypes.Structure):
@@ -103,6 +104,8 @@ class EikOptions(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("stats", ctypes.POINTER(EikStats)),
         ("spacing", ctypes.c_double * 3),
+        ("order_min", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
     ]
 
 
@@ -186,7 +189,8 @@ def _check(rc: int):
 def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[Sequence[int]] = None,
                  inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
                  skip_remedy: bool = False, async_: bool = False, profile: bool = False,
-                 fifo: bool = False, spacing: Optional[Sequence[float]] = None) -> EikOptions:
+                 fifo: bool = False, spacing: Optional[Sequence[float]] = None, order_min: int = 0,
+                 workgroups: int = 0) -> EikOptions:
     o = EikOptions()
     _load().eik_default_options(ctypes.byref(o))
     if dtype is not None:
@@ -207,6 +211,8 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
     if spacing is not None:
         for k, v in enumerate(spacing):
             o.spacing[k] = float(v)
+    o.order_min = int(order_min)
+    o.workgroups = int(workgroups)
     return o
 
 
@@ -285,7 +291,8 @@ def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[st
           source_values=None, deterministic: bool = False, skip_remedy: bool = False,
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
           out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False,
-          async_: bool = False, fifo: bool = False, spacing: Optional[Sequence[float]] = None):
+          async_: bool = False, fifo: bool = False, spacing: Optional[Sequence[float]] = None,
+          order_min: int = 0, workgroups: int = 0):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
@@ -298,7 +305,8 @@ def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[st
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, async_=async_, profile=profile, fifo=fifo, spacing=spacing)
+                       skip_remedy, async_=async_, profile=profile, fifo=fifo, spacing=spacing,
+                       order_min=order_min, workgroups=workgroups)
     h = 1.0 if h is None and spacing is not None else h
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
@@ -334,7 +342,7 @@ def solve_noalloc(F, h: Optional[float], sources, eps: float = 0.0, *, out=None,
                   variant: Union[str, int] = "tile", source_values=None, deterministic: bool = False,
                   skip_remedy: bool = False, tile: Optional[Sequence[int]] = None, inner_iters: int = 0,
                   max_iters: int = 0, stats: bool = False, stream=None, fifo: bool = False,
-                  spacing: Optional[Sequence[float]] = None):
+                  spacing: Optional[Sequence[float]] = None, order_min: int = 0, workgroups: int = 0):
     """eik_solve_noalloc: solve() on the library's static device scratch (no
     workspace argument; the library allocates nothing).  Synchronous only.
     Pass `out` to keep the call free of allocations on this side too."""
@@ -343,7 +351,7 @@ def solve_noalloc(F, h: Optional[float], sources, eps: float = 0.0, *, out=None,
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, fifo=fifo, spacing=spacing)
+                       skip_remedy, fifo=fifo, spacing=spacing, order_min=order_min, workgroups=workgroups)
     h = 1.0 if h is None and spacing is not None else h
     dims = _dims(F.shape)
     src = _sources_array(sources, F.shape)
@@ -485,7 +493,7 @@ def eik_batch_workspace_size(shapes, h, sources, opt: Optional[EikOptions] = Non
 def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
                 tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0, out=None,
                 workspace=None, stats: bool = False, stream=None, profile: bool = False, async_: bool = False,
-                fifo: bool = False):
+                fifo: bool = False, order_min: int = 0, workgroups: int = 0):
     """Solve several independent grids in one call (tile schedule).
 
     F: flat device tensor with the grids back to back (see pack()); shapes:
@@ -498,7 +506,7 @@ def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
     if F.numel() != sum(batch_sizes(shapes)):
         raise ValueError("F must hold exactly the grids of the batch")
     opt = make_options(_dtype_code(F), "tile", tile, inner_iters, max_iters, async_=async_, profile=profile,
-                       fifo=fifo)
+                       fifo=fifo, order_min=order_min, workgroups=workgroups)
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     vals = None
@@ -570,8 +578,8 @@ def adjoint_batch(F, phi, shapes, h, sources, dL_dphi, *, out=None, workspace=No
 def tune(F, h: Optional[float], sources, eps: float = 0.0, *, stream=None, workspace=None,
          spacing: Optional[Sequence[float]] = None, fifo: bool = False):
     """Time the tile-variant candidates on this problem (eik_tune) and return
-    {"tile": (z, y, x), "inner_iters": k, "candidates": [...]} -- pass tile and
-    inner_iters to solve().  Cached per (ndim, dtype, log2 N, per-axis spacing
+    {"tile": (z, y, x), "inner_iters": k, "order_min": m, "workgroups": w,
+    "candidates": [...]} -- pass them to solve().  Cached per (ndim, dtype, log2 N, per-axis spacing
     or not, remedy schedule) for the process; a cached answer reports no
     candidates.  fifo: tune the first-in first-out remedy schedule."""
     torch = _torch()
@@ -593,8 +601,10 @@ def tune(F, h: Optional[float], sources, eps: float = 0.0, *, stream=None, works
                               scratch.data_ptr(), ctypes.byref(opt), rep, 16, ctypes.byref(nrep))
     _check(rc)
     cands = [{"tile": tuple(int(v) for v in rep[k].tile), "inner_iters": int(rep[k].inner_iters),
+              "order_min": int(rep[k].order_min), "workgroups": int(rep[k].workgroups),
               "ms": float(rep[k].ms)} for k in range(nrep.value)]
-    return {"tile": tuple(int(v) for v in opt.tile), "inner_iters": int(opt.inner_iters), "candidates": cands}
+    return {"tile": tuple(int(v) for v in opt.tile), "inner_iters": int(opt.inner_iters),
+            "order_min": int(opt.order_min), "workgroups": int(opt.workgroups), "candidates": cands}
 
 
 def _make_eikonal_fn():

@@ -465,7 +465,7 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     // with tag 1 and the tag chain starts at tag[0] = 1 (claims 2, 3, ...)
     auto iter_args = [&](int64_t t) {
         AdjIter<T> a{};
-        sched_fill(a, w.q, t, ordered, ND, static_cast<int>(t & 1), 1, w.ctl, w.blkstat);
+        sched_fill(a, w.q, t, ordered, order_min_of(ND, o.order_min), static_cast<int>(t & 1), 1, w.ctl, w.blkstat);
         a.phi = phi;
         a.g = g;
         a.lam = static_cast<T*>(w.lam);
@@ -496,7 +496,8 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
             if (e != hipSuccess) return e;
         }
         return timed(prof, EIK_KERNEL_ADJOINT, [&] {
-            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(GT), dim3(kBlock), 0, s, a, G, inner);
+            hipLaunchKernelGGL((k_adj_tile<T, ND, TX, TY, TZ>), dim3(workgroups_of(ND, o.workgroups)), dim3(kBlock), 0,
+                               s, a, G, inner);
             return hipGetLastError();
         });
     };

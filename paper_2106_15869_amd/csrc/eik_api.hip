@@ -100,6 +100,9 @@ static eik_status check_options(const eik_options& o) {
         return fail(EIK_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
     for (int k = 0; k < 3; ++k)
         if (o.tile[k] < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "tile extents must be >= 0");
+    if (o.order_min < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "order_min must be >= 0");
+    if (o.workgroups < 0 || o.workgroups > kMaxStatBlocks || o.workgroups % kWorkgroupStep)
+        return fail(EIK_ERR_INVALID_ARGUMENT, "workgroups must be 0 or a multiple of 8 up to 2048");
     return EIK_OK;
 }
 

@@ -41,6 +41,23 @@ enum StatField {
 };
 constexpr int kMaxStatBlocks = 2048;
 
+// Persistent workgroups of a tile launch: a multiple of kWorkgroupStep (the
+// sub-lists of a tile list) up to kMaxStatBlocks; by default six resident
+// per CU on 256 CUs in 3D, 2048 in 2D (eik_options.workgroups).
+constexpr int kWorkgroupStep = 8;
+inline int default_workgroups(int nd) { return nd == 3 ? 1536 : 2048; }
+// The persistent workgroups a call uses (eik_options.workgroups, 0: default).
+inline int workgroups_of(int nd, int32_t opt) { return opt > 0 ? opt : default_workgroups(nd); }
+
+// Ordered remedy: a launch takes at least this many of the queued tiles with
+// the lowest order keys.  In 3D 1024; a 2D front is a curve and keeps fewer
+// tiles final at a time, 512 (measured: maze 256^3 best at 1024, layered
+// 192^3 5 % faster at 512, 2D lognormal 4096^2 and the paper's Example 5 at
+// 4000^2 3-4 % faster at 512 than at 1024; eik_tune times both).
+inline int order_min(int nd) { return nd == 2 ? 512 : 1024; }
+// The per-launch minimum a call uses (eik_options.order_min, 0: default).
+inline int order_min_of(int nd, int32_t opt) { return opt > 0 ? opt : order_min(nd); }
+
 // Internal option bit, added after the caller's options are checked (callers
 // cannot set it): a synchronous call reads its list lengths and results back
 // through pageable host memory instead of the per-thread pinned slots and

@@ -13,10 +13,11 @@
 namespace eik {
 namespace {
 
-// Persistent workgroups per tile launch; group k = blockIdx % kSub drains
-// sub-list k of the launch's tile list.
-constexpr int GT = 2048;
-constexpr int kSub = 8;       // sub-lists per tile list
+// Persistent workgroups of a tile launch (eik_options.workgroups, a multiple
+// of kSub); group k = blockIdx % kSub drains sub-list k of the launch's tile
+// list.  GT is the most a launch takes.
+constexpr int GT = kMaxStatBlocks;
+constexpr int kSub = kWorkgroupStep;  // sub-lists per tile list
 static_assert(GT % kSub == 0, "each sub-list has the same number of workgroups");
 constexpr int kPad = 32;      // ints between counters (separate cache lines)
 // Dirty-face mask bit meaning "recheck every node of the tile".
@@ -24,13 +25,11 @@ constexpr uint32_t kAllFaces = 64u;
 // Ordered remedy: per-tile order keys (monotone 32-bit images of the
 // smallest value that made the tile pending), a histogram of them over kBins
 // bins (the top key bits: sign, exponent and the leading mantissa bits), and
-// the number of lowest-key tiles a launch processes at least: in 3D 1024; a
-// 2D front is a curve and keeps fewer tiles final at a time, 512 (measured:
-// maze 256^3 and layered 192^3 best at 1024, 2D lognormal 4096^2 and the
-// paper's Example 5 at 4000^2 3-4 % faster at 512 than at 1024).
+// the number of lowest-key tiles a launch processes at least (order_min in
+// eik_internal.hpp).
 constexpr int kBins = 8192;
 constexpr int kBinShift = 32 - 13;  // kBins = 2^13
-inline int order_min(int nd) { return nd == 2 ? 512 : 1024; }
+
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 
@@ -495,7 +494,7 @@ SchedWs sched_layout(Take&& take, int64_t ntiles) {
 // Launch t of a loop drains list t and fills list t + 1 (the counter set of
 // list t + 2 is cleared by launch t); tag_slot is the parity in the device
 // tag chain.
-inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int nd, int tag_slot, int phase,
+inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int omin, int tag_slot, int phase,
                        Ctl* ctl, unsigned long long* blkstat) {
     const size_t nt = static_cast<size_t>(w.ntiles);
     a.tstamp = w.tstamp;
@@ -506,7 +505,7 @@ inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int 
     a.hist_cur = w.hist_of(static_cast<int>(t % 3));
     a.hist_next = w.hist_of(static_cast<int>((t + 1) % 3));
     a.ordered = ordered ? 1 : 0;
-    a.order_min = order_min(nd);
+    a.order_min = omin;
     a.work = w.work_of(t);
     a.work_zero_count = w.work_of(t + 1).count;
     a.work_zero_fetch = w.work_of(t + 1).fetch;

@@ -759,27 +759,28 @@ bool update_tiling(const Batch& b, const eik_options& o, TileCfg& cu) {
     return true;
 }
 
+// Launches of `gt` persistent workgroups (a multiple of kSub, at most GT).
 template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 struct TileKernels {
-    static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
+    static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, int gt, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
-    static hipError_t detect(const TileIter<T>& a, const BatchGeom<T>& g, T eps, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps);
+    static hipError_t detect(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int gt, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_detect<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps);
         return hipGetLastError();
     }
-    static hipError_t remedy(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ, AN>), dim3(GT), dim3(kBlock), 0, s, a, g, eps, inner);
+    static hipError_t remedy(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, int gt, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
 };
 
 template <typename T>
 struct TileOps {
-    hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
-    hipError_t (*detect)(const TileIter<T>&, const BatchGeom<T>&, T, hipStream_t) = nullptr;
-    hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
+    hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*detect)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
+    hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
 };
 
 template <typename T, int ND, int TX, int TY, int TZ, bool AN = false>
@@ -893,6 +894,8 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     const int side_u = std::max(cu.tx, std::max(cu.ty, cu.tz));
     const int inner_upd = o.inner_iters > 0 ? o.inner_iters : (b.nd == 2 ? side_u : inner);
     const int ntiles_u = static_cast<int>(B2.ntiles);
+    const int gt = workgroups_of(b.nd, o.workgroups);
+    const int omin = order_min_of(b.nd, o.order_min);
     int64_t launched = 0;
 
     Profiler prof;
@@ -952,7 +955,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     // and three counter sets (the set of list t + 2 is cleared by launch t)
     auto iter_args = [&](int64_t t, int phase) {
         TileIter<T> a{};
-        sched_fill(a, w.q, t, ordered && phase == 1, b.nd, static_cast<int>((gl + t) & 1), phase, w.ctl,
+        sched_fill(a, w.q, t, ordered && phase == 1, omin, static_cast<int>((gl + t) & 1), phase, w.ctl,
                    w.blkstat);
         a.F = F;
         a.phi = phi;
@@ -964,7 +967,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     int64_t n2 = 0;
     eik_status rc = run_loop(
         [&](int64_t t) {
-            return timed(prof, EIK_KERNEL_UPDATE, [&] { return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, s); });
+            return timed(prof, EIK_KERNEL_UPDATE, [&] { return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, gt, s); });
         },
         counts, kSub * kPad, cap, async, s, &n2, w.ctl, pageable);
     gl += n2;
@@ -979,7 +982,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         d.hist_next = w.q.hist_of(0);
         d.first = 0;
         d.tag_slot = static_cast<int>(gl & 1);
-        HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, geom, eT, s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_DETECT, [&] { return k.detect(d, geom, eT, gt, s); }));
         gl += 1;
         launched += 2;
         int64_t n3 = 0;
@@ -994,7 +997,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
                     });
                     if (e != hipSuccess) return e;
                 }
-                return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(a, geom, eT, inner, s); });
+                return timed(prof, EIK_KERNEL_REMEDY, [&] { return k.remedy(a, geom, eT, inner, gt, s); });
             },
             counts, kSub * kPad, cap, async, s, &n3, w.ctl, pageable);
         launched += (ordered ? 2 : 1) * n3;

@@ -1,7 +1,8 @@
-// eik_tune: per-problem choice of the tile shape and inner-iteration cap of
-// the tile variant, by timing candidates with HIP events on the caller's
-// stream.  Choices are cached per (ndim, dtype, log2 N, per-axis spacing
-// or not, remedy schedule flags) for the process.
+// eik_tune: per-problem choice of the tile variant's schedule -- tile shape
+// and inner-iteration cap, then the ordered remedy's per-launch minimum and
+// the persistent workgroups per launch -- by timing candidates with HIP events
+// on the caller's stream.  Choices are cached per (ndim, dtype, log2 N,
+// per-axis spacing or not, remedy schedule flags) for the process.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,6 +23,8 @@ namespace {
 struct Choice {
     int32_t tile[3];
     int32_t inner;
+    int32_t order_min = 0;   // 0: default
+    int32_t workgroups = 0;  // 0: default
 };
 
 std::mutex g_tune_mu;
@@ -112,12 +115,16 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
             opt->variant = EIK_VARIANT_TILE;
             std::memcpy(opt->tile, it->second.tile, sizeof(opt->tile));
             opt->inner_iters = it->second.inner;
+            opt->order_min = it->second.order_min;
+            opt->workgroups = it->second.workgroups;
             return EIK_OK;
         }
     }
     eik_options base = *opt;
     base.variant = EIK_VARIANT_TILE;
     base.stats = nullptr;
+    base.order_min = 0;
+    base.workgroups = 0;
     const std::vector<Choice> cand = candidates(ndim, aniso);
     size_t need = 0;
     for (const Choice& c : cand) {
@@ -142,11 +149,14 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     double best = 0.0;
     Choice pick = cand[0];
     int32_t written = 0;
-    for (const Choice& c : cand) {
+    // warm-up solve, then the best of two timed ones; the fastest so far is kept
+    auto trial = [&](const Choice& c) -> eik_status {
         eik_options q = base;
         std::memcpy(q.tile, c.tile, sizeof(q.tile));
         q.inner_iters = c.inner;
-        eik_status rc = eik_solve(F, ndim, dims, h, sources, n_sources, eps, phi_scratch, &q);  // warm-up
+        q.order_min = c.order_min;
+        q.workgroups = c.workgroups;
+        eik_status rc = eik_solve(F, ndim, dims, h, sources, n_sources, eps, phi_scratch, &q);
         if (rc != EIK_OK) return rc;
         double ms_best = 0.0;
         for (int rep = 0; rep < 2; ++rep) {
@@ -164,11 +174,38 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
             std::memcpy(e.tile, c.tile, sizeof(e.tile));
             e.inner_iters = c.inner;
             e.ms = ms_best;
+            e.order_min = c.order_min;
+            e.workgroups = c.workgroups;
         }
         if (best == 0.0 || ms_best < best) {
             best = ms_best;
             pick = c;
         }
+        return EIK_OK;
+    };
+    for (const Choice& c : cand) {
+        const eik_status rc = trial(c);
+        if (rc != EIK_OK) return rc;
+    }
+    // launch parameters for the chosen shape: the ordered remedy's per-launch
+    // minimum (when the remedy runs ordered), then the workgroups per launch
+    const Choice shape = pick;
+    if (!(base.flags & kScheduleFlags)) {
+        const int om = order_min_of(ndim, 0);
+        for (int v : {om / 2, 2 * om}) {
+            Choice c = shape;
+            c.order_min = v;
+            const eik_status rc = trial(c);
+            if (rc != EIK_OK) return rc;
+        }
+    }
+    const Choice launch = pick;
+    for (int v : {1024, 1536, 2048}) {
+        if (v == workgroups_of(ndim, 0)) continue;  // timed already
+        Choice c = launch;
+        c.workgroups = v;
+        const eik_status rc = trial(c);
+        if (rc != EIK_OK) return rc;
     }
     if (n_report) *n_report = written;
     {
@@ -178,5 +215,7 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     opt->variant = EIK_VARIANT_TILE;
     std::memcpy(opt->tile, pick.tile, sizeof(opt->tile));
     opt->inner_iters = pick.inner;
+    opt->order_min = pick.order_min;
+    opt->workgroups = pick.workgroups;
     return EIK_OK;
 }

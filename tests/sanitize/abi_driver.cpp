@@ -240,6 +240,13 @@ static void noalloc_validation() {
     CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &far, 1, 0.0, kPhi, nullptr) == EIK_ERR_INVALID_ARGUMENT,
           "noalloc source range");
     CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kF, nullptr) == EIK_ERR_INVALID_ARGUMENT, "noalloc alias");
+    eik_options wg = defaults();
+    wg.workgroups = 12;
+    CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &wg) == EIK_ERR_INVALID_ARGUMENT, "noalloc workgroups");
+    CHECK(eik_solve(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &wg) == EIK_ERR_INVALID_ARGUMENT, "solve workgroups");
+    eik_options om = defaults();
+    om.order_min = -3;
+    CHECK(eik_solve(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &om) == EIK_ERR_INVALID_ARGUMENT, "solve order_min");
     eik_options f = defaults();
     f.flags = 1u << 31;
     CHECK(eik_solve_noalloc(kF, 2, d2, 1.0, &s0, 1, 0.0, kPhi, &f) == EIK_ERR_INVALID_ARGUMENT, "noalloc flags");

@@ -48,11 +48,14 @@ def test_default_options(lib):
     lib.eik_default_options(ctypes.byref(o))
     assert o.dtype == eik.EIK_FLOAT32 and o.variant == eik.EIK_VARIANT_TILE
     assert o.flags == 0 and o.max_iters == 0 and not o.workspace
+    assert o.order_min == 0 and o.workgroups == 0
 
 
 def test_options_struct_layout():
     # mirrors eik_options in include/eik.h on LP64
-    assert ctypes.sizeof(eik.EikOptions) == 104
+    assert ctypes.sizeof(eik.EikOptions) == 112
+    assert eik.EikOptions.order_min.offset == 104 and eik.EikOptions.workgroups.offset == 108
+    assert ctypes.sizeof(eik.EikTuneEntry) == 32
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
     assert ctypes.sizeof(eik.EikStats) == 120 + 80
@@ -64,9 +67,11 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "eik.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options), sizeof(eik_stats),'
-        ' offsetof(eik_options, max_iters), offsetof(eik_options, stats), offsetof(eik_stats, evals_check),'
-        ' offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms), offsetof(eik_options, spacing));'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options),'
+        ' sizeof(eik_stats), offsetof(eik_options, max_iters), offsetof(eik_options, stats),'
+        ' offsetof(eik_stats, evals_check), offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms),'
+        ' offsetof(eik_options, spacing), offsetof(eik_options, order_min), offsetof(eik_options, workgroups),'
+        ' sizeof(eik_tune_entry), offsetof(eik_tune_entry, order_min), offsetof(eik_tune_entry, workgroups));'
         ' return 0; }\n')
     exe = tmp_path / "layout"
     import subprocess
@@ -74,7 +79,9 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(eik.EikOptions), ctypes.sizeof(eik.EikStats), eik.EikOptions.max_iters.offset,
             eik.EikOptions.stats.offset, eik.EikStats.evals_check.offset, eik.EikStats.kernel_launches.offset,
-            eik.EikStats.kernel_ms.offset, eik.EikOptions.spacing.offset]
+            eik.EikStats.kernel_ms.offset, eik.EikOptions.spacing.offset, eik.EikOptions.order_min.offset,
+            eik.EikOptions.workgroups.offset, ctypes.sizeof(eik.EikTuneEntry), eik.EikTuneEntry.order_min.offset,
+            eik.EikTuneEntry.workgroups.offset]
     assert got == want
 
 
@@ -333,3 +340,19 @@ def test_noalloc_rejects_before_device_work(lib):
     bad = eik.make_options(eik.EIK_FLOAT32, "tile")
     bad.flags = 1 << 31
     assert _noalloc_raw(lib, (8, 8), bad) == eik.EIK_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("field,value,ok", [
+    ("order_min", -1, False), ("order_min", 1, True), ("order_min", 4096, True),
+    ("workgroups", -8, False), ("workgroups", 12, False), ("workgroups", 2056, False),
+    ("workgroups", 8, True), ("workgroups", 1536, True), ("workgroups", 2048, True),
+])
+def test_schedule_options_validated(lib, field, value, ok):
+    """order_min >= 0; workgroups 0 or a multiple of 8 up to 2048 (host checks,
+    before device work: the valid ones are seen through the size query)."""
+    o = eik.make_options(eik.EIK_FLOAT32, "tile", **{field: value})
+    if ok:
+        assert eik.eik_workspace_size((16, 16), o) > 0
+    else:
+        assert _solve_raw(lib, (4, 4), opt=o) == eik.EIK_ERR_INVALID_ARGUMENT
+        assert field.split("_")[0] in lib.eik_last_error().decode()

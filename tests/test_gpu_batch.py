@@ -141,14 +141,50 @@ def test_graph_capture_replays(variant):
 
 @pytest.mark.parametrize("P", [W.lognormal_2d(300, seed=4), W.maze_3d(48)], ids=lambda P: P.name)
 def test_tune_picks_a_candidate_and_caches_it(P):
+    """eik_tune times the shapes, then the ordered remedy's per-launch minimum
+    (half and twice the default) and the workgroups per launch for the chosen
+    shape; it returns the fastest candidate, caches it, and the choice solves
+    within the float32 gate."""
     F = torch.from_numpy(P.F).to(DEV)
     t = eik.tune(F, P.h, P.sources)
-    assert t["candidates"], "first call for this size class times candidates"
-    assert (t["tile"], t["inner_iters"]) in {(c["tile"], c["inner_iters"]) for c in t["candidates"]}
-    assert min(c["ms"] for c in t["candidates"]) == pytest.approx(
-        [c["ms"] for c in t["candidates"] if (c["tile"], c["inner_iters"]) == (t["tile"], t["inner_iters"])][0])
+    cands = t["candidates"]
+    assert cands, "first call for this size class times candidates"
+
+    def key(c):
+        return (c["tile"], c["inner_iters"], c["order_min"], c["workgroups"])
+
+    assert key(t) in {key(c) for c in cands}
+    assert min(c["ms"] for c in cands) == pytest.approx([c["ms"] for c in cands if key(c) == key(t)][0])
+    default_om = 512 if P.F.ndim == 2 else 1024
+    assert {c["order_min"] for c in cands} == {0, default_om // 2, 2 * default_om}
+    assert {c["workgroups"] for c in cands} == ({0, 1024, 2048} if P.F.ndim == 3 else {0, 1024, 1536})
     again = eik.tune(F, P.h, P.sources)
-    assert again["candidates"] == [] and again["tile"] == t["tile"] and again["inner_iters"] == t["inner_iters"]
-    phi = eik.solve(F, P.h, P.sources, tile=t["tile"], inner_iters=t["inner_iters"]).cpu().numpy()
+    assert again["candidates"] == [] and key(again) == key(t)
+    phi = eik.solve(F, P.h, P.sources, tile=t["tile"], inner_iters=t["inner_iters"], order_min=t["order_min"],
+                    workgroups=t["workgroups"]).cpu().numpy()
     ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
     assert np.max(np.abs(phi - ref)) <= 1e-5 * ref.max()
+
+
+@pytest.mark.parametrize("order_min,workgroups", [(1, 8), (64, 1024), (4096, 2048), (0, 8)])
+@pytest.mark.parametrize("P", [W.lognormal_2d(200, seed=6), W.maze_3d(48), W.layered_3d(40)],
+                         ids=lambda P: P.name)
+def test_schedule_options_keep_the_fixed_point(P, order_min, workgroups):
+    """Explicit per-launch minimum of the ordered remedy and persistent
+    workgroups per launch (down to 8, one per sub-list) change only the order
+    of the tile visits: the result meets the float32 gate, for a single grid
+    and for a batch of two."""
+    print(f"[case] {P.name} order_min {order_min} workgroups {workgroups}", flush=True)
+    F = torch.from_numpy(P.F).to(DEV)
+    ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+    fin = np.isfinite(ref)
+    phi = eik.solve(F, P.h, P.sources, order_min=order_min, workgroups=workgroups).cpu().numpy()
+    assert np.array_equal(fin, np.isfinite(phi))
+    assert np.max(np.abs(phi[fin] - ref[fin])) <= 1e-5 * ref[fin].max()
+    Fb = torch.cat([F.reshape(-1), F.reshape(-1)])
+    pb = eik.solve_batch(Fb, [P.F.shape] * 2, P.h, [P.sources] * 2, order_min=order_min,
+                         workgroups=workgroups).cpu().numpy()
+    for k in range(2):
+        part = pb[k * P.F.size:(k + 1) * P.F.size].reshape(P.F.shape)
+        assert np.array_equal(fin, np.isfinite(part))
+        assert np.max(np.abs(part[fin] - ref[fin])) <= 1e-5 * ref[fin].max()
