@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
     unsigned long long visits = 0;
     for (bool first = true;; first = false) {
         if (threadIdx.x == 0) {
-            const int e = fetch_index(src, k, first);
+            const int e = fetch_index(src, k, len, first);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
             if (tt >= 0) {

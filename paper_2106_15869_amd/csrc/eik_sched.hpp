@@ -255,22 +255,25 @@ __device__ __forceinline__ int list_open(const Sched& a, int* s_len, int* s_wlen
 // current list itself (k_tile_split moved nothing to the work list).
 __device__ __forceinline__ bool list_direct(const Sched& a, int n) { return a.ordered && n <= a.order_min; }
 
-// Index of the next entry of sub-list k a workgroup takes (grids of a
-// multiple of kSub workgroups).  Its first entry is fixed, blockIdx / kSub:
-// the gridDim / kSub workgroups of group k cover the first gridDim / kSub
-// entries without an atomic (a launch's opening fetches would otherwise
-// queue on the group's counter).  Later entries come from the fetch counter,
-// offset past them.
-__device__ __forceinline__ int fetch_index(const TList& L, int k, bool first) {
+// Index of the next entry of sub-list k (of `len` entries) a workgroup takes
+// (grids of a multiple of kSub workgroups).  Its first entry is fixed,
+// blockIdx / kSub: the gridDim / kSub workgroups of group k cover the first
+// gridDim / kSub entries without an atomic (a launch's opening fetches would
+// otherwise queue on the group's counter).  Later entries come from the
+// fetch counter, offset past them -- unless the fixed entries already cover
+// the sub-list, when a workgroup is done after its first visit.
+__device__ __forceinline__ int fetch_index(const TList& L, int k, int len, bool first) {
     const int fixed = static_cast<int>(gridDim.x) / kSub;
-    return first ? static_cast<int>(blockIdx.x) / kSub : fixed + atomicAdd(L.fetch + k * kPad, 1);
+    if (first) return static_cast<int>(blockIdx.x) / kSub;
+    if (len <= fixed) return len;
+    return fixed + atomicAdd(L.fetch + k * kPad, 1);
 }
 
 // Next entry of sub-list k for this workgroup (-1 when drained).  Lane 0
 // fetches; the value is broadcast through LDS.
 __device__ __forceinline__ int list_fetch(const TList& L, int k, int len, int* s_slot, bool first) {
     if (threadIdx.x == 0) {
-        const int e = fetch_index(L, k, first);
+        const int e = fetch_index(L, k, len, first);
         *s_slot = e < len ? L.data[static_cast<size_t>(k) * L.cap + e] : -1;
     }
     __syncthreads();

@@ -111,7 +111,11 @@ __device__ __forceinline__ void load_owned_F(const Inst<T>& g, int x0, int y0, i
 // Stage the tile and its halo: values (+inf outside) and labels (kOut outside).
 // Addresses are clamped into the grid, so every global load of a lane is
 // issued unconditionally, before its first LDS store (one memory round trip).
-template <typename T, int ND, int TX, int TY, int TZ>
+// Without HALO_LABELS only the tile's own labels are loaded (the halo's are
+// set to 0, or kOut outside the grid): the detection pass and the remedy read
+// labels of in-tile nodes only, and a halo row of labels is a cache line for
+// ten bytes.
+template <typename T, int ND, int TX, int TY, int TZ, bool HALO_LABELS = true>
 __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, const T* phi,
                                       const uint8_t* lab, T* sphi, uint8_t* sl) {
     using S = Shape<ND, TX, TY, TZ>;
@@ -131,7 +135,8 @@ __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, 
         const int cx = min(max(gx, 0), g.nx - 1), cy = min(max(gy, 0), g.ny - 1), cz = min(max(gz, 0), g.nz - 1);
         const int G = g.node_base + (cz * g.ny + cy) * g.nx + cx;
         v[j] = phi[G];
-        l[j] = lab[G];
+        const bool inner = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && (ND == 2 || (lz >= 1 && lz <= TZ));
+        l[j] = (HALO_LABELS || inner) ? lab[G] : uint8_t(0);
     }
 #pragma unroll
     for (int j = 0; j < NIT; ++j) {
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         if (threadIdx.x == 0) s_key = kNoKey;  // ordered below the staging barrier
-        stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        stage<T, ND, TX, TY, TZ, false>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
         Owned<T, S::NPT> o;
         own_nodes<T, ND, TX, TY, TZ, AN>(g, x0, y0, z0, a.F, o);
         __syncthreads();
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
     unsigned long long evals = 0, inner_sum = 0, written = 0, visits = 0;
     for (bool first = true;; first = false) {
         if (threadIdx.x == 0) {
-            const int e = fetch_index(src, k, first);
+            const int e = fetch_index(src, k, len, first);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
             const int tt = e < len ? src.data[idx] : -1;
             if (e < len && from_work) {
@@ -547,7 +552,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
         }
         T fv[S::NPT];
         load_owned_F<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, fv);
-        stage<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        stage<T, ND, TX, TY, TZ, false>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             const int nn = threadIdx.x + r * kBlock;
