@@ -322,16 +322,17 @@ eik_status eik_async_status(const void* workspace, void* stream);
  * (serving loops and harnesses that forbid allocation): same arguments,
  * checks, schedules and results as eik_solve, but the call allocates nothing
  * -- no device memory, no pinned host memory, no HIP events.  Its workspace
- * is a static device array of 64 MiB (67108864 bytes) that each GPU the
+ * is a static device array of 128 MiB (134217728 bytes) that each GPU the
  * library runs on holds from the first use until the process ends; results
  * are read back through pageable host memory.
  *   Arguments as eik_solve.  opt->workspace must be NULL (and
  *   workspace_bytes 0); EIK_FLAG_ASYNC and EIK_FLAG_PROFILE are not accepted
  *   (EIK_ERR_UNSUPPORTED): the call is synchronous.
  * Errors as eik_solve, and EIK_ERR_OUT_OF_MEMORY, before any device work,
- * when eik_workspace_size for the shape and options exceeds 64 MiB (e.g. the
- * tile variant takes 25 MiB at 256^3 and 34 MiB at 4096^2; the node-list
- * variants need about 60 bytes per node and fit up to about 1 M nodes).
+ * when eik_workspace_size for the shape and options exceeds 128 MiB (e.g.
+ * the tile variant takes 89 MiB at 256^3 and 98 MiB at 4096^2 in float32;
+ * the node-list variants need about 60 bytes per node and fit up to about
+ * 2 M nodes).
  * Every call on one GPU shares that GPU's array, which keeps the last
  * call's contents (each solve initialises what it reads); calls that overlap
  * on one GPU -- from several host threads or on several streams -- race on it

@@ -31,7 +31,7 @@
 namespace eik {
 namespace {
 
-constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchBytes = size_t(128) << 20;
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];

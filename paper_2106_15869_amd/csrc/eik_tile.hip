@@ -51,6 +51,7 @@ struct TileIter : Sched {
     const T* F;
     T* phi;
     uint8_t* lab;
+    const T* cells;  // tile-major cell values (k_build_cells), read by detection and the remedy
 };
 
 
@@ -71,18 +72,17 @@ template <typename T, bool AN>
 __device__ __forceinline__ bool cell_live(T v) {
     return AN ? v > T(0) : v < pos_inf<T>();
 }
-
-// Per-lane description of the nodes a lane owns in the current tile.
-template <typename T, int NPT>
-struct Owned {
-    int G[NPT];      // global index
-    int L[NPT];      // LDS index (with halo)
-    int face[NPT];   // bit d set: node on the tile face in direction d (-x,+x,-y,+y,-z,+z)
-                     // and the grid continues across it
-    int edge[NPT];   // bit d set: node on the tile face in direction d
-    T H[NPT];
-    bool ok[NPT];
-};
+// The tile-major cell array marks a fixed (source) node with -1, a value no
+// cell_value takes.
+template <typename T>
+__device__ __forceinline__ T fixed_cell() {
+    return T(-1);
+}
+// whether a cell-array entry belongs to a node the remedy may change
+template <typename T, bool AN>
+__device__ __forceinline__ bool cell_free(T v) {
+    return cell_live<T, AN>(v) && !(v < T(0));
+}
 
 // Global index of in-tile node n (clamped into the grid, so that it can be
 // loaded unconditionally) and whether the node lies in the grid.
@@ -115,7 +115,8 @@ __device__ __forceinline__ void load_owned_F(const Inst<T>& g, int x0, int y0, i
 // set to 0, or kOut outside the grid): the detection pass and the remedy read
 // labels of in-tile nodes only, and a halo row of labels is a cache line for
 // ten bytes.
-template <typename T, int ND, int TX, int TY, int TZ, bool HALO_LABELS = true>
+// With LABELS false no labels are loaded or stored (sl may be null).
+template <typename T, int ND, int TX, int TY, int TZ, bool HALO_LABELS = true, bool LABELS = true>
 __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, const T* phi,
                                       const uint8_t* lab, T* sphi, uint8_t* sl) {
     using S = Shape<ND, TX, TY, TZ>;
@@ -136,52 +137,15 @@ __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, 
         const int G = g.node_base + (cz * g.ny + cy) * g.nx + cx;
         v[j] = phi[G];
         const bool inner = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && (ND == 2 || (lz >= 1 && lz <= TZ));
-        l[j] = (HALO_LABELS || inner) ? lab[G] : uint8_t(0);
+        l[j] = LABELS && (HALO_LABELS || inner) ? lab[G] : uint8_t(0);
     }
 #pragma unroll
     for (int j = 0; j < NIT; ++j) {
         const int q = threadIdx.x + j * kBlock;
         if (q < S::NL) {
             sphi[q] = in[j] ? v[j] : inf;
-            sl[q] = in[j] ? l[j] : static_cast<uint8_t>(kOut);
+            if (LABELS) sl[q] = in[j] ? l[j] : static_cast<uint8_t>(kOut);
         }
-    }
-}
-
-template <typename T, int ND, int TX, int TY, int TZ, bool AN>
-__device__ __forceinline__ void own_nodes(const Inst<T>& g, int x0, int y0, int z0, const T* F,
-                                          Owned<T, Shape<ND, TX, TY, TZ>::NPT>& o) {
-    using S = Shape<ND, TX, TY, TZ>;
-#pragma unroll
-    for (int r = 0; r < S::NPT; ++r) {
-        const int n = threadIdx.x + r * kBlock;
-        const int x = n % TX, y = (n / TX) % TY, z = ND == 3 ? n / (TX * TY) : 0;
-        const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
-        o.ok[r] = n < S::NT && gx < g.nx && gy < g.ny && gz < g.nz;
-        o.G[r] = g.node_base + (gz * g.ny + gy) * g.nx + gx;
-        o.L[r] = ND == 3 ? ((z + 1) * S::LY + (y + 1)) * S::LX + (x + 1) : (y + 1) * S::LX + (x + 1);
-        int e = 0;
-        if (x == 0) e |= 1;
-        if (x == TX - 1) e |= 2;
-        if (y == 0) e |= 4;
-        if (y == TY - 1) e |= 8;
-        if (ND == 3) {
-            if (z == 0) e |= 16;
-            if (z == TZ - 1) e |= 32;
-        }
-        o.edge[r] = e;
-        int f = 0;
-        if (x == 0 && gx > 0) f |= 1;
-        if (x == TX - 1 && gx + 1 < g.nx) f |= 2;
-        if (y == 0 && gy > 0) f |= 4;
-        if (y == TY - 1 && gy + 1 < g.ny) f |= 8;
-        if (ND == 3) {
-            if (z == 0 && gz > 0) f |= 16;
-            if (z == TZ - 1 && gz + 1 < g.nz) f |= 32;
-        }
-        o.face[r] = f;
-        o.H[r] = dead_value<T, AN>();
-        if (o.ok[r]) o.H[r] = cell_value<T, AN>(g, F[o.G[r]]);
     }
 }
 
@@ -437,7 +401,6 @@ template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom<T> bg, T eps) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
-    __shared__ uint8_t sl[S::NL];
     __shared__ uint32_t s_key;
     const uint32_t ntag = launch_tag(a);
     for (int t = blockIdx.x; t < bg.ntiles; t += gridDim.x) {
@@ -446,17 +409,24 @@ __global__ __launch_bounds__(kBlock) void k_tile_detect(TileIter<T> a, BatchGeom
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         if (threadIdx.x == 0) s_key = kNoKey;  // ordered below the staging barrier
-        stage<T, ND, TX, TY, TZ, false>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
-        Owned<T, S::NPT> o;
-        own_nodes<T, ND, TX, TY, TZ, AN>(g, x0, y0, z0, a.F, o);
+        T hv[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
+            hv[r] = a.cells[static_cast<size_t>(t) * S::NT + nn];
+        }
+        stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, a.phi, nullptr, sphi, nullptr);
         __syncthreads();
         bool flag = false;
         T low = pos_inf<T>();
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
-            if (!o.ok[r] || (sl[o.L[r]] & 3u) == L_FIXED) continue;
-            const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, o.L[r], o.H[r], g);
-            if (pt < sphi[o.L[r]] - eps) {
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn >= S::NT || !cell_free<T, AN>(hv[r])) continue;  // outside, barrier or fixed
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, L, hv[r], g);
+            if (pt < sphi[L] - eps) {
                 flag = true;
                 low = tmin(low, pt);
             }
@@ -492,7 +462,6 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
     TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
-    __shared__ uint8_t sl[S::NL];
     __shared__ T sH[S::NT];
     __shared__ TileLists<S::NT> tl;
     __shared__ int s_len[kSub];
@@ -550,16 +519,18 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
             }
             s_kmin = kNoKey;
         }
-        T fv[S::NPT];
-        load_owned_F<T, ND, TX, TY, TZ>(g, x0, y0, z0, a.F, fv);
-        stage<T, ND, TX, TY, TZ, false>(g, x0, y0, z0, a.phi, a.lab, sphi, sl);
+        T hv[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
+            hv[r] = a.cells[static_cast<size_t>(t) * S::NT + nn];
+        }
+        stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, a.phi, nullptr, sphi, nullptr);
 #pragma unroll
         for (int r = 0; r < S::NPT; ++r) {
             const int nn = threadIdx.x + r * kBlock;
             if (nn < S::NT) {
-                bool ok;
-                owned_index<T, ND, TX, TY, TZ>(g, x0, y0, z0, nn, ok);
-                sH[nn] = ok ? cell_value<T, AN>(g, fv[r]) : dead_value<T, AN>();
+                sH[nn] = hv[r];
                 tl.flag[0][nn] = 0u;
                 tl.flag[1][nn] = 0u;
                 tl.dirty[nn] = 0;
@@ -584,8 +555,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
             int x, y, z, L;
             node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
             const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
-            const bool live = cell_live<T, AN>(sH[nn]) && (sl[L] & 3u) != L_FIXED;
-            if (live && ((m & kAllFaces) || (E & static_cast<int>(m))))
+            if (cell_free<T, AN>(sH[nn]) && ((m & kAllFaces) || (E & static_cast<int>(m))))
                 tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
         }
         __syncthreads();
@@ -624,8 +594,8 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
                                 kmin = tmin(kmin, pt);
                             }
                         } else {
-                            const uint8_t lb = sl[Ln];
-                            if (!(lb & kOut) && (lb & 3u) != L_FIXED) list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
+                            const int qn = q + node_step<TX, TY>(d);
+                            if (cell_free<T, AN>(sH[qn])) list_add(tl, nb, ncnt, qn);
                         }
                     }
                 }
@@ -682,6 +652,36 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
 
 
 // ---------------------------------------------------------------------------
+// Tile-major cell values
+// ---------------------------------------------------------------------------
+// Entry t * NT + n holds the cell value of node n of tile t (H = h / F, or F
+// itself with per-axis spacing; +inf / 0 on a barrier), -1 for a fixed node,
+// the dead value outside the grid.  Built once per solve after the update
+// step: a tile's detection and remedy visits then read one contiguous block
+// instead of a row of F per cache line and a label byte per node, and do not
+// divide.  (NT is a multiple of 64, so a wave's entries share one tile.)
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
+__global__ __launch_bounds__(kBlock) void k_build_cells(BatchGeom<T> bg, const T* __restrict__ F,
+                                                        const uint8_t* __restrict__ lab, T* __restrict__ cells) {
+    using S = Shape<ND, TX, TY, TZ>;
+    static_assert(S::NT % 64 == 0, "a wave's entries must lie in one tile");
+    const int64_t total = static_cast<int64_t>(bg.ntiles) * S::NT;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int t = static_cast<int>(i / S::NT);
+        const int n = static_cast<int>(i - static_cast<int64_t>(t) * S::NT);
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
+        bool ok;
+        const int G = owned_index<T, ND, TX, TY, TZ>(g, tx * TX, ty * TY, tz * (ND == 3 ? TZ : 1), n, ok);
+        T v = dead_value<T, AN>();
+        if (ok) v = (lab[G] & 3u) == L_FIXED ? fixed_cell<T>() : cell_value<T, AN>(g, F[G]);
+        cells[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // STEP 1 helpers
 // ---------------------------------------------------------------------------
 
@@ -721,6 +721,7 @@ struct TileWs {
     Ctl* ctl;
     unsigned long long* blkstat;
     uint8_t* lab;
+    void* cells;        // tile-major cell values (ntiles x tile nodes)
     SchedWs q;          // lists, stamps, masks, keys, histograms, work lists
     void* table;        // instance table (batches of more than one instance)
     int* tile_inst;     // instance of every tile (idem)
@@ -729,7 +730,8 @@ struct TileWs {
     size_t bytes;
 };
 
-TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t inst_bytes, bool two_tilings) {
+TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t inst_bytes, bool two_tilings,
+                   size_t cell_bytes) {
     TileWs w{};
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -740,6 +742,7 @@ TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t i
     w.ctl = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
     w.blkstat = reinterpret_cast<unsigned long long*>(take(8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks));
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
+    w.cells = take(cell_bytes);
     w.q = sched_layout(take, ntiles);
     if (ninst > 1) {
         w.table = take(inst_bytes * ninst);
@@ -779,6 +782,13 @@ struct TileKernels {
         hipLaunchKernelGGL((k_tile_remedy<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps, inner);
         return hipGetLastError();
     }
+    static hipError_t cells(const BatchGeom<T>& g, const T* F, const uint8_t* lab, T* out, hipStream_t s) {
+        using S = Shape<ND, TX, TY, TZ>;
+        const int64_t total = static_cast<int64_t>(g.ntiles) * S::NT;
+        const int blocks = static_cast<int>(std::min<int64_t>((total + kBlock - 1) / kBlock, 8192));
+        hipLaunchKernelGGL((k_build_cells<T, ND, TX, TY, TZ, AN>), dim3(blocks), dim3(kBlock), 0, s, g, F, lab, out);
+        return hipGetLastError();
+    }
 };
 
 template <typename T>
@@ -786,6 +796,7 @@ struct TileOps {
     hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
     hipError_t (*detect)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
     hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*cells)(const BatchGeom<T>&, const T*, const uint8_t*, T*, hipStream_t) = nullptr;
 };
 
 template <typename T, int ND, int TX, int TY, int TZ, bool AN = false>
@@ -794,6 +805,7 @@ TileOps<T> ops_of() {
     k.update = &TileKernels<T, ND, TX, TY, TZ, AN>::update;
     k.detect = &TileKernels<T, ND, TX, TY, TZ, AN>::detect;
     k.remedy = &TileKernels<T, ND, TX, TY, TZ, AN>::remedy;
+    k.cells = &TileKernels<T, ND, TX, TY, TZ, AN>::cells;
     return k;
 }
 
@@ -863,9 +875,14 @@ Batch with_tiles(const Batch& b, const TileCfg& c) {
     return r;
 }
 
+// Bytes of the tile-major cell array of a batch's tiling.
+static size_t cell_array_bytes(const Batch& b, size_t esz) {
+    return static_cast<size_t>(b.ntiles) * static_cast<size_t>(b.cfg.tx) * b.cfg.ty * b.cfg.tz * esz;
+}
+
 size_t tile_workspace_bytes(const Batch& b, size_t esz) {
     const size_t ib = esz == 8 ? sizeof(Inst<double>) : sizeof(Inst<float>);
-    return tile_layout(nullptr, b.n, b.ntiles, b.inst.size(), ib, b.nd == 2).bytes;
+    return tile_layout(nullptr, b.n, b.ntiles, b.inst.size(), ib, b.nd == 2, cell_array_bytes(b, esz)).bytes;
 }
 
 template <typename T>
@@ -878,7 +895,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     if (!select_ops<T>(b.nd, c, b.inst[0].aniso != 0, k))
         return fail(EIK_ERR_INVALID_ARGUMENT, b.inst[0].aniso ? "per-axis spacing needs the default tile shape"
                                                               : "unsupported tile shape");
-    TileWs w = tile_layout(ws, b.n, b.ntiles, b.inst.size(), sizeof(Inst<T>), b.nd == 2);
+    TileWs w = tile_layout(ws, b.n, b.ntiles, b.inst.size(), sizeof(Inst<T>), b.nd == 2, cell_array_bytes(b, sizeof(T)));
     // the update step's tiling (the same unless update_tiling says otherwise)
     TileCfg cu = c;
     const bool two = update_tiling(b, o, cu);
@@ -965,6 +982,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         a.F = F;
         a.phi = phi;
         a.lab = w.lab;
+        a.cells = static_cast<const T*>(w.cells);
         return a;
     };
     auto counts = [&](int64_t t) { return w.q.count_of(static_cast<int>(t % 3)); };
@@ -978,7 +996,11 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     gl += n2;
     launched += n2;
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
-        // detection fills list 0 of the remedy loop
+        // tile-major cell values for detection and the remedy; detection
+        // fills list 0 of the remedy loop
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
+                      [&] { return k.cells(geom, F, w.lab, static_cast<T*>(w.cells), s); }));
+        launched += 1;
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.q.counters, kCounterBytes, s); }));
         TileIter<T> d = iter_args(0, 1);  // only `next` (list 0), its masks and the tag are used
         d.next = list_of(0);

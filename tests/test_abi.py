@@ -315,15 +315,15 @@ def _noalloc_raw(lib, dims, opt=None, F=0x1000, phi=0x2000, sources=(0,)):
 
 def test_noalloc_rejects_before_device_work(lib):
     """eik_solve_noalloc answers these on the host: a problem whose workspace
-    exceeds the 64 MiB static scratch, a caller workspace, asynchronous or
+    exceeds the 128 MiB static scratch, a caller workspace, asynchronous or
     profiled calls, and eik_solve's own argument checks."""
     big = (512, 512, 512)
     o = eik.make_options(eik.EIK_FLOAT32, "tile")
-    assert eik.eik_workspace_size(big, o) > 64 << 20
+    assert eik.eik_workspace_size(big, o) > 128 << 20
     assert _noalloc_raw(lib, big, o) == eik.EIK_ERR_OUT_OF_MEMORY
     assert b"static scratch" in lib.eik_last_error()
     node = eik.make_options(eik.EIK_FLOAT32, "node")
-    assert eik.eik_workspace_size((2048, 2048), node) > 64 << 20
+    assert eik.eik_workspace_size((2048, 2048), node) > 128 << 20
     assert _noalloc_raw(lib, (2048, 2048), node) == eik.EIK_ERR_OUT_OF_MEMORY
     ws = eik.make_options(eik.EIK_FLOAT32, "tile")
     ws.workspace = 0x10000
