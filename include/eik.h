@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define EIK_ABI_VERSION 7
+#define EIK_ABI_VERSION 8
 
 typedef enum {
     EIK_OK = 0,
@@ -90,7 +90,16 @@ enum {
        by a histogram of per-tile keys) and defers the others, so corrections
        flow roughly in increasing value and fewer nodes are corrected twice.
        Same rules and fixed point either way. */
-    EIK_FLAG_FIFO_REMEDY = 16u
+    EIK_FLAG_FIFO_REMEDY = 16u,
+    /* 3D tile variant: run the update step alone.  By default the persistent
+       workgroups that find no update-step tile in a launch run remedy visits
+       meanwhile (every node of a tile whose update visits left no active
+       node, first-in first-out, stopping when the launch's update visits are
+       done), so corrections start behind the front instead of after the
+       step; the detection pass and remedy loop that follow are unchanged
+       and decide the fixed point (eik_stats.evals_early counts these
+       evaluations). */
+    EIK_FLAG_NO_EARLY_REMEDY = 32u
 };
 
 /* Kernel kinds of eik_stats.kernel_ms / kernel_launches. */
@@ -120,6 +129,7 @@ typedef struct {
     int64_t written_step2;      /* node values written back to HBM in the update step */
     int64_t written_step3;      /* ... in the remedy loop */
     int64_t evals_check;        /* FIM: evaluations of neighbours of converged nodes */
+    int64_t evals_early;        /* 3D tile variant: remedy evaluations run during the update step */
     int64_t kernel_launches[EIK_KERNEL_KINDS]; /* with EIK_FLAG_PROFILE */
     double kernel_ms[EIK_KERNEL_KINDS];        /* with EIK_FLAG_PROFILE: summed device time */
 } eik_stats;

@@ -44,12 +44,13 @@ EIK_FLOAT64 = 1
 EIK_VARIANT_NODE_LIST = 0
 EIK_VARIANT_TILE = 1
 EIK_VARIANT_FIM = 2
-EIK_ABI_VERSION = 7
+EIK_ABI_VERSION = 8
 EIK_FLAG_DETERMINISTIC = 1
 EIK_FLAG_SKIP_REMEDY = 2
 EIK_FLAG_ASYNC = 4
 EIK_FLAG_PROFILE = 8
 EIK_FLAG_FIFO_REMEDY = 16
+EIK_FLAG_NO_EARLY_REMEDY = 32
 
 VARIANTS = {"node": EIK_VARIANT_NODE_LIST, "node_list": EIK_VARIANT_NODE_LIST,
             "tile": EIK_VARIANT_TILE, "fim": EIK_VARIANT_FIM}
@@ -79,7 +80,8 @@ class EikStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "step2_iters", "step3_iters", "evals_step2", "evals_detect", "evals_remedy",
         "remedy_initial", "max_active", "launches", "tile_visits_step2", "tile_visits_step3",
-        "inner_step2", "inner_step3", "written_step2", "written_step3", "evals_check")] + [
+        "inner_step2", "inner_step3", "written_step2", "written_step3", "evals_check",
+        "evals_early")] + [
         ("kernel_launches", ctypes.c_int64 * 5), ("kernel_ms", ctypes.c_double * 5)]
 
     def to_dict(self):
@@ -190,7 +192,7 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
                  inner_iters: int = 0, max_iters: int = 0, deterministic: bool = False,
                  skip_remedy: bool = False, async_: bool = False, profile: bool = False,
                  fifo: bool = False, spacing: Optional[Sequence[float]] = None, order_min: int = 0,
-                 workgroups: int = 0) -> EikOptions:
+                 workgroups: int = 0, early: bool = True) -> EikOptions:
     o = EikOptions()
     _load().eik_default_options(ctypes.byref(o))
     if dtype is not None:
@@ -207,7 +209,8 @@ def make_options(dtype=None, variant: Union[str, int] = "tile", tile: Optional[S
                (EIK_FLAG_SKIP_REMEDY if skip_remedy else 0) |
                (EIK_FLAG_ASYNC if async_ else 0) |
                (EIK_FLAG_PROFILE if profile else 0) |
-               (EIK_FLAG_FIFO_REMEDY if fifo else 0))
+               (EIK_FLAG_FIFO_REMEDY if fifo else 0) |
+               (0 if early else EIK_FLAG_NO_EARLY_REMEDY))
     if spacing is not None:
         for k, v in enumerate(spacing):
             o.spacing[k] = float(v)
@@ -292,12 +295,14 @@ def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[st
           tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0,
           out=None, workspace=None, stats: bool = False, stream=None, profile: bool = False,
           async_: bool = False, fifo: bool = False, spacing: Optional[Sequence[float]] = None,
-          order_min: int = 0, workgroups: int = 0):
+          order_min: int = 0, workgroups: int = 0, early: bool = True):
     """Solve ||grad phi|| = 1/F on F's grid (2D or 3D device tensor).
 
     sources: flat indices, or an (n, ndim) array of coordinates.  Returns phi
     (and a stats dict when stats=True).  fifo=True runs the tile variant's
-    remedy first-in first-out instead of in increasing pending value.  async_=True only enqueues (no host
+    remedy first-in first-out instead of in increasing pending value;
+    early=False keeps the 3D tile variant's idle workgroups out of the update
+    step (no early remedy visits).  async_=True only enqueues (no host
     synchronisation, capturable in a graph): it needs `workspace`, `out` and
     an explicit `max_iters`, and runs exactly max_iters launches per loop."""
     torch = _torch()
@@ -306,7 +311,7 @@ def solve(F, h: Optional[float], sources, eps: float = 0.0, *, variant: Union[st
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
                        skip_remedy, async_=async_, profile=profile, fifo=fifo, spacing=spacing,
-                       order_min=order_min, workgroups=workgroups)
+                       order_min=order_min, workgroups=workgroups, early=early)
     h = 1.0 if h is None and spacing is not None else h
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
@@ -342,7 +347,8 @@ def solve_noalloc(F, h: Optional[float], sources, eps: float = 0.0, *, out=None,
                   variant: Union[str, int] = "tile", source_values=None, deterministic: bool = False,
                   skip_remedy: bool = False, tile: Optional[Sequence[int]] = None, inner_iters: int = 0,
                   max_iters: int = 0, stats: bool = False, stream=None, fifo: bool = False,
-                  spacing: Optional[Sequence[float]] = None, order_min: int = 0, workgroups: int = 0):
+                  spacing: Optional[Sequence[float]] = None, order_min: int = 0, workgroups: int = 0,
+                  early: bool = True):
     """eik_solve_noalloc: solve() on the library's static device scratch (no
     workspace argument; the library allocates nothing).  Synchronous only.
     Pass `out` to keep the call free of allocations on this side too."""
@@ -351,7 +357,8 @@ def solve_noalloc(F, h: Optional[float], sources, eps: float = 0.0, *, out=None,
     if F.dim() not in (2, 3):
         raise ValueError("F must be 2D or 3D")
     opt = make_options(_dtype_code(F), variant, tile, inner_iters, max_iters, deterministic,
-                       skip_remedy, fifo=fifo, spacing=spacing, order_min=order_min, workgroups=workgroups)
+                       skip_remedy, fifo=fifo, spacing=spacing, order_min=order_min, workgroups=workgroups,
+                       early=early)
     h = 1.0 if h is None and spacing is not None else h
     dims = _dims(F.shape)
     src = _sources_array(sources, F.shape)
@@ -493,7 +500,7 @@ def eik_batch_workspace_size(shapes, h, sources, opt: Optional[EikOptions] = Non
 def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
                 tile: Optional[Sequence[int]] = None, inner_iters: int = 0, max_iters: int = 0, out=None,
                 workspace=None, stats: bool = False, stream=None, profile: bool = False, async_: bool = False,
-                fifo: bool = False, order_min: int = 0, workgroups: int = 0):
+                fifo: bool = False, order_min: int = 0, workgroups: int = 0, early: bool = True):
     """Solve several independent grids in one call (tile schedule).
 
     F: flat device tensor with the grids back to back (see pack()); shapes:
@@ -506,7 +513,7 @@ def solve_batch(F, shapes, h, sources, eps: float = 0.0, *, source_values=None,
     if F.numel() != sum(batch_sizes(shapes)):
         raise ValueError("F must hold exactly the grids of the batch")
     opt = make_options(_dtype_code(F), "tile", tile, inner_iters, max_iters, async_=async_, profile=profile,
-                       fifo=fifo, order_min=order_min, workgroups=workgroups)
+                       fifo=fifo, order_min=order_min, workgroups=workgroups, early=early)
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
     vals = None

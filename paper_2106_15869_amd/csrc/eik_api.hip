@@ -86,7 +86,7 @@ static eik_status check_options(const eik_options& o) {
         return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_VARIANT_FIM has no remedy step to skip");
     if (o.max_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "max_iters must be >= 0");
     if (o.inner_iters < 0) return fail(EIK_ERR_INVALID_ARGUMENT, "inner_iters must be >= 0");
-    if (o.flags & ~31u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
+    if (o.flags & ~63u) return fail(EIK_ERR_INVALID_ARGUMENT, "unknown flag bits");
     if ((o.flags & EIK_FLAG_FIFO_REMEDY) && o.variant != EIK_VARIANT_TILE)
         return fail(EIK_ERR_INVALID_ARGUMENT, "EIK_FLAG_FIFO_REMEDY needs the tile variant");
     if ((o.flags & EIK_FLAG_ASYNC) && (o.flags & EIK_FLAG_PROFILE))

@@ -494,6 +494,21 @@ SchedWs sched_layout(Take&& take, int64_t ntiles) {
     return w;
 }
 
+// Scheduling state of an unordered (first-in first-out) tile loop only:
+// stamps, dirty-face masks, counters and the two list buffers, each sub-list
+// sized for the tiles of its residue class (no keys, no work lists).
+template <typename Take>
+SchedWs early_layout(Take&& take, int64_t ntiles) {
+    SchedWs w{};
+    w.cap = static_cast<int>(ntiles / kSub + 64);
+    w.ntiles = static_cast<int>(ntiles);
+    w.tstamp = reinterpret_cast<uint32_t*>(take(4 * static_cast<size_t>(ntiles)));
+    w.tmask = reinterpret_cast<uint32_t*>(take(8 * static_cast<size_t>(ntiles)));
+    w.counters = reinterpret_cast<int*>(take(kCounterBytes));
+    for (int k = 0; k < 2; ++k) w.data[k] = reinterpret_cast<int*>(take(4 * static_cast<size_t>(w.cap) * kSub));
+    return w;
+}
+
 // Launch t of a loop drains list t and fills list t + 1 (the counter set of
 // list t + 2 is cleared by launch t); tag_slot is the parity in the device
 // tag chain.
@@ -521,6 +536,13 @@ inline void sched_fill(Sched& a, const SchedWs& w, int64_t t, bool ordered, int 
     a.tag_slot = tag_slot;
     a.phase = phase;
     a.first = (phase == 1 && t == 0) ? 1 : 0;
+}
+
+// Before a solve, for an early_layout state: stamps, masks and counters zero.
+inline hipError_t early_clear(const SchedWs& w, hipStream_t s) {
+    hipError_t e = launch_zero_words(w.tstamp, 4 * (static_cast<size_t>(w.tmask - w.tstamp) + 2 * static_cast<size_t>(w.ntiles)), s);
+    if (e == hipSuccess) e = launch_zero_words(w.counters, kCounterBytes, s);
+    return e;
 }
 
 // Before a solve: stamps and masks zero, list counters and histograms zero,

@@ -52,6 +52,12 @@ struct TileIter : Sched {
     T* phi;
     uint8_t* lab;
     const T* cells;  // tile-major cell values (k_build_cells), read by detection and the remedy
+    // early remedy visits during the update step (3D): per tile whether its
+    // last update visit left no active node, and the update visits finished
+    // in this launch and in the next one (cleared by this one)
+    uint8_t* done;
+    int* fin;
+    int* fin_clear;
 };
 
 
@@ -175,8 +181,19 @@ __device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& 
 // ---------------------------------------------------------------------------
 // STEP 2 on tiles
 // ---------------------------------------------------------------------------
+// Resident workgroups per CU for the update step: six for 8^3 float tiles
+// (two nodes per lane), so that all 1536 default workgroups of a launch are
+// resident at once (eighty registers, no spills); with early remedy visits a
+// workgroup that waited for a slot would start its visit late and hold the
+// launch.  Others unconstrained.
+template <int ND, int NPT, typename T>
+constexpr int update_blocks_per_cu() {
+    return ND == 3 && NPT == 2 && sizeof(T) == 4 ? 6 : 1;
+}
+
 template <typename T, int ND, int TX, int TY, int TZ, bool AN>
-__global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom<T> bg, T eps, int inner) {
+__global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY, TZ>::NPT, T>())) void k_tile_update(
+    TileIter<T> a, BatchGeom<T> bg, T eps, int inner, TileIter<T> e, int early_inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T sphi[S::NL];
     __shared__ uint8_t sl[S::NL];
@@ -188,8 +205,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
     __shared__ int s_face;
     __shared__ int s_evals;
     __shared__ int s_written;
+    __shared__ int s_elen[kSub];
+    __shared__ uint32_t s_emask;
+    __shared__ int s_stop;
     const T inf = pos_inf<T>();
     const uint32_t ntag = launch_tag(a);
+    const bool early = e.done != nullptr;
+    if (early) {
+        __builtin_amdgcn_s_setprio(2);
+        if (blockIdx.x == 0 && threadIdx.x < kSub) {
+            e.zero_count[threadIdx.x * kPad] = 0;
+            e.zero_fetch[threadIdx.x * kPad] = 0;
+            if (threadIdx.x == 0) *e.fin_clear = 0;
+        }
+        if (threadIdx.x < kSub) s_elen[threadIdx.x] = e.cur.count[threadIdx.x * kPad];
+    }
     const int n = list_open(a, s_len);
     launch_stats(a, n);
     // workgroups of group k take entries of sub-list k one at a time
@@ -374,7 +404,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             const int d = threadIdx.x;
             const int fmask = s_face;
             if (d == 6) {
-                if (any_active) push_tile(a.next, a.tstamp, t, ntag);
+                if (any_active) {
+                    push_tile(a.next, a.tstamp, t, ntag);
+                } else if (early) {
+                    // the tile's update work is done for now: queue its first
+                    // remedy visit (every node) for the idle workgroups
+                    e.done[t] = 1;
+                    atomicOr(e.mask_next + t, kAllFaces);
+                    push_tile(e.next, e.tstamp, t, ntag);
+                }
             } else if (d < 2 * ND && (fmask & (1 << d))) {
                 push_tile(a.next, a.tstamp, neighbour_tile(g, t, d), ntag);
             }
@@ -383,6 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
             evals += static_cast<unsigned long long>(s_evals);
             inner_sum += static_cast<unsigned long long>(it);
             written += static_cast<unsigned long long>(s_written);
+            if (early) atomicAdd(e.fin, 1);
         }
         __syncthreads();
     }
@@ -392,6 +431,146 @@ __global__ __launch_bounds__(kBlock) void k_tile_update(TileIter<T> a, BatchGeom
         stat_add(a.blkstat, SF_INNER2, inner_sum);
         stat_add(a.blkstat, SF_WRITTEN2, written);
     }
+    // Early remedy: workgroups that had no update visit in this launch run
+    // remedy visits (first-in first-out, at most early_inner inner
+    // iterations) on tiles whose update work is done, behind the front; the
+    // remedy after the update step (detection over every node, then the
+    // ordered loop) still decides the fixed point.
+    if (!early || visits) return;
+    __builtin_amdgcn_s_setprio(0);  // below the update visits still running on this CU
+    const int elen = s_elen[k];
+    unsigned long long eevals = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            // no new early visit once the launch's update visits are all done
+            const bool over = __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n;
+            const int ei = over ? elen : atomicAdd(e.cur.fetch + k * kPad, 1);  // workgroups arrive at any time
+            const int tt = ei < elen ? e.cur.data[static_cast<size_t>(k) * e.cur.cap + ei] : -1;
+            if (tt >= 0) {
+                s_emask = e.mask_cur[tt];  // set by an earlier launch; no writer during this one
+                e.mask_cur[tt] = 0u;
+            }
+            s_slot = tt;
+        }
+        __syncthreads();
+        const int t = s_slot;
+        __syncthreads();
+        if (t < 0) break;
+        const Inst<T> g = inst_of(bg, t);
+        const int lt = t - g.tile_base;
+        const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
+        const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
+        T hv[S::NPT];
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
+            hv[r] = e.cells[static_cast<size_t>(t) * S::NT + nn];
+        }
+        stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, a.phi, nullptr, sphi, nullptr);
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn < S::NT) {
+                sH[nn] = hv[r];
+                tl.flag[0][nn] = 0u;
+                tl.flag[1][nn] = 0u;
+                tl.dirty[nn] = 0;
+            }
+        }
+        if (threadIdx.x == 0) {
+            s_face = 0;
+            s_evals = 0;
+            s_stop = 0;
+            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
+        }
+        __syncthreads();
+        const uint32_t m = s_emask;
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn >= S::NT) continue;
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
+            if (cell_free<T, AN>(sH[nn]) && ((m & kAllFaces) || (E & static_cast<int>(m))))
+                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
+        }
+        __syncthreads();
+        bool pending = false;
+        int my_evals = 0, fm = 0;
+        for (int it = 0;; ++it) {
+            const int ncur = tl.cnt[it % 3];
+            if (ncur == 0) break;
+            if (it == early_inner || s_stop) {  // the launch's update visits are done
+                pending = true;
+                break;
+            }
+            const int cb = it & 1, nb = cb ^ 1;
+            int* ncnt = &tl.cnt[(it + 1) % 3];
+            if (threadIdx.x == 0) {
+                tl.cnt[(it + 2) % 3] = 0;
+                if (it & 1) s_stop = __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n;
+            }
+            for (int i = threadIdx.x; i < ncur; i += kBlock) {
+                const int q = tl.list[cb][i];
+                tl.flag[cb][q] = 0u;
+                int x, y, z, Lq;
+                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+                ++my_evals;
+                const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
+                if (pt < sphi[Lq] - eps) {
+                    sphi[Lq] = pt;
+                    tl.dirty[q] = 1;
+                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
+#pragma unroll
+                    for (int d = 0; d < 2 * ND; ++d) {
+                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                        if (!(pt < sphi[Ln])) continue;
+                        if (edge & (1 << d)) {
+                            if (open & (1 << d)) fm |= 1 << d;
+                        } else {
+                            const int qn = q + node_step<TX, TY>(d);
+                            if (cell_free<T, AN>(sH[qn])) list_add(tl, nb, ncnt, qn);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (fm) atomicOr(&s_face, fm);
+        if (my_evals) atomicAdd(&s_evals, my_evals);
+        __syncthreads();
+        // a face whose neighbour tile is done with its update work marks that
+        // tile; the others get their first visit when they are done
+        if (threadIdx.x < 7) {
+            const int d = threadIdx.x;
+            if (d == 6) {
+                if (pending) {
+                    atomicOr(e.mask_next + t, kAllFaces);
+                    push_tile(e.next, e.tstamp, t, ntag);
+                }
+            } else if (d < 2 * ND && (s_face & (1 << d))) {
+                const int tn = neighbour_tile(g, t, d);
+                if (e.done[tn]) {
+                    atomicOr(e.mask_next + tn, 1u << (d ^ 1));
+                    push_tile(e.next, e.tstamp, tn, ntag);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < S::NPT; ++r) {
+            const int nn = threadIdx.x + r * kBlock;
+            if (nn >= S::NT || !tl.dirty[nn]) continue;
+            int x, y, z, L;
+            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+            a.phi[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = sphi[L];
+        }
+        if (threadIdx.x == 0) eevals += static_cast<unsigned long long>(s_evals);
+        __syncthreads();
+        break;  // one early visit per workgroup and launch: the launch ends with its update visits
+    }
+    if (threadIdx.x == 0) stat_add(a.blkstat, SF_CHECK, eevals);
 }
 
 // ---------------------------------------------------------------------------
@@ -723,6 +902,8 @@ struct TileWs {
     uint8_t* lab;
     void* cells;        // tile-major cell values (ntiles x tile nodes)
     SchedWs q;          // lists, stamps, masks, keys, histograms, work lists
+    SchedWs eq;         // 3D: the early remedy's lists, stamps and dirty-face masks
+    uint8_t* done;      // 3D: per tile, update work done
     void* table;        // instance table (batches of more than one instance)
     int* tile_inst;     // instance of every tile (idem)
     void* table_u;      // the same for the update step's tiling (2D, see solve_tile)
@@ -744,6 +925,10 @@ TileWs tile_layout(char* base, int64_t n, int64_t ntiles, size_t ninst, size_t i
     w.lab = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(n)));
     w.cells = take(cell_bytes);
     w.q = sched_layout(take, ntiles);
+    if (!two_tilings) {  // 3D (one tiling for both steps): early remedy
+        w.eq = early_layout(take, ntiles);
+        w.done = reinterpret_cast<uint8_t*>(take(static_cast<size_t>(ntiles)));
+    }
     if (ninst > 1) {
         w.table = take(inst_bytes * ninst);
         w.tile_inst = reinterpret_cast<int*>(take(4 * static_cast<size_t>(ntiles)));
@@ -770,8 +955,10 @@ bool update_tiling(const Batch& b, const eik_options& o, TileCfg& cu) {
 // Launches of `gt` persistent workgroups (a multiple of kSub, at most GT).
 template <typename T, int ND, int TX, int TY, int TZ, bool AN>
 struct TileKernels {
-    static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, int gt, hipStream_t s) {
-        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps, inner);
+    static hipError_t update(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int inner, int gt,
+                             const TileIter<T>& e, int early_inner, hipStream_t s) {
+        hipLaunchKernelGGL((k_tile_update<T, ND, TX, TY, TZ, AN>), dim3(gt), dim3(kBlock), 0, s, a, g, eps, inner, e,
+                           early_inner);
         return hipGetLastError();
     }
     static hipError_t detect(const TileIter<T>& a, const BatchGeom<T>& g, T eps, int gt, hipStream_t s) {
@@ -793,7 +980,8 @@ struct TileKernels {
 
 template <typename T>
 struct TileOps {
-    hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
+    hipError_t (*update)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, const TileIter<T>&, int,
+                         hipStream_t) = nullptr;
     hipError_t (*detect)(const TileIter<T>&, const BatchGeom<T>&, T, int, hipStream_t) = nullptr;
     hipError_t (*remedy)(const TileIter<T>&, const BatchGeom<T>&, T, int, int, hipStream_t) = nullptr;
     hipError_t (*cells)(const BatchGeom<T>&, const T*, const uint8_t*, T*, hipStream_t) = nullptr;
@@ -937,6 +1125,8 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return sched_clear(w.q, s); }));
     launched += 7;
     const bool ordered = (o.flags & EIK_FLAG_FIFO_REMEDY) == 0;
+    const bool early = b.nd == 3 && sizeof(T) == 4 && !two &&
+                       !(o.flags & (EIK_FLAG_NO_EARLY_REMEDY | EIK_FLAG_SKIP_REMEDY));
     std::vector<SrcBatch<T>> batches;
     for (size_t q = 0; q < b.src.size(); q += kMaxSrcBatch) {
         SrcBatch<T> sb{};
@@ -986,11 +1176,36 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         return a;
     };
     auto counts = [&](int64_t t) { return w.q.count_of(static_cast<int>(t % 3)); };
+    if (early) {
+        // cell values (sources are fixed by now) and the early remedy's lists
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return k.cells(geom, F, w.lab, static_cast<T*>(w.cells), s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return early_clear(w.eq, s); }));
+        HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
+                      [&] { return launch_zero_words(w.done, align_up(static_cast<size_t>(b.ntiles), 4), s); }));
+        launched += 3;
+    }
+    auto early_args = [&](int64_t t) {
+        TileIter<T> e{};
+        if (!early) return e;
+        sched_fill(e, w.eq, t, false, omin, static_cast<int>((gl + t) & 1), 1, w.ctl, w.blkstat);
+        e.phi = phi;
+        e.cells = static_cast<const T*>(w.cells);
+        e.done = w.done;
+        e.fin = &w.ctl->cnt[t % 3];
+        e.fin_clear = &w.ctl->cnt[(t + 1) % 3];
+        return e;
+    };
+    // inner iterations of an early remedy visit (maze 256^3 / layered 192^3:
+    // 16 gave 14.1 / 5.9 ms, 32 and 64 14.7 / 6.3 ms: deeper visits hold the
+    // update launch longer than they shorten the remedy loop)
+    const int early_inner = 16;
 
     int64_t n2 = 0;
     eik_status rc = run_loop(
         [&](int64_t t) {
-            return timed(prof, EIK_KERNEL_UPDATE, [&] { return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, gt, s); });
+            return timed(prof, EIK_KERNEL_UPDATE, [&] {
+                return ku.update(iter_args(t, 0), geom_u, eT, inner_upd, gt, early_args(t), early_inner, s);
+            });
         },
         counts, kSub * kPad, cap, async, s, &n2, w.ctl, pageable);
     gl += n2;
@@ -998,9 +1213,11 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
     if (rc == EIK_OK && !(o.flags & EIK_FLAG_SKIP_REMEDY)) {
         // tile-major cell values for detection and the remedy; detection
         // fills list 0 of the remedy loop
-        HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
-                      [&] { return k.cells(geom, F, w.lab, static_cast<T*>(w.cells), s); }));
-        launched += 1;
+        if (!early) {
+            HIP_TRY(timed(prof, EIK_KERNEL_OTHER,
+                          [&] { return k.cells(geom, F, w.lab, static_cast<T*>(w.cells), s); }));
+            launched += 1;
+        }
         HIP_TRY(timed(prof, EIK_KERNEL_OTHER, [&] { return launch_zero_words(w.q.counters, kCounterBytes, s); }));
         TileIter<T> d = iter_args(0, 1);  // only `next` (list 0), its masks and the tag are used
         d.next = list_of(0);
@@ -1050,6 +1267,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         st->inner_step3 = static_cast<int64_t>(res.sum[SF_INNER3]);
         st->written_step2 = static_cast<int64_t>(res.sum[SF_WRITTEN2]);
         st->written_step3 = static_cast<int64_t>(res.sum[SF_WRITTEN3]);
+        st->evals_early = static_cast<int64_t>(res.sum[SF_CHECK]);
         HIP_TRY(prof.collect(st));
     }
     return rc;

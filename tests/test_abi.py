@@ -58,7 +58,8 @@ def test_options_struct_layout():
     assert ctypes.sizeof(eik.EikTuneEntry) == 32
     assert eik.EikOptions.max_iters.offset == 24
     assert eik.EikOptions.stats.offset == 72
-    assert ctypes.sizeof(eik.EikStats) == 120 + 80
+    assert ctypes.sizeof(eik.EikStats) == 128 + 80
+    assert eik.EikStats.evals_early.offset == 120
 
 
 def test_struct_layout_matches_c_compiler(tmp_path):
@@ -67,9 +68,10 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "eik.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options),'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eik_options),'
         ' sizeof(eik_stats), offsetof(eik_options, max_iters), offsetof(eik_options, stats),'
-        ' offsetof(eik_stats, evals_check), offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms),'
+        ' offsetof(eik_stats, evals_check), offsetof(eik_stats, evals_early),'
+        ' offsetof(eik_stats, kernel_launches), offsetof(eik_stats, kernel_ms),'
         ' offsetof(eik_options, spacing), offsetof(eik_options, order_min), offsetof(eik_options, workgroups),'
         ' sizeof(eik_tune_entry), offsetof(eik_tune_entry, order_min), offsetof(eik_tune_entry, workgroups));'
         ' return 0; }\n')
@@ -78,7 +80,8 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(eik.EikOptions), ctypes.sizeof(eik.EikStats), eik.EikOptions.max_iters.offset,
-            eik.EikOptions.stats.offset, eik.EikStats.evals_check.offset, eik.EikStats.kernel_launches.offset,
+            eik.EikOptions.stats.offset, eik.EikStats.evals_check.offset, eik.EikStats.evals_early.offset,
+            eik.EikStats.kernel_launches.offset,
             eik.EikStats.kernel_ms.offset, eik.EikOptions.spacing.offset, eik.EikOptions.order_min.offset,
             eik.EikOptions.workgroups.offset, ctypes.sizeof(eik.EikTuneEntry), eik.EikTuneEntry.order_min.offset,
             eik.EikTuneEntry.workgroups.offset]

@@ -216,3 +216,32 @@ def test_workspace_reuse_and_streams():
     s.synchronize()
     assert_close(a.cpu().numpy(), ref_solve(P1, np.float32), np.float32)
     assert_close(b.cpu().numpy(), ref_solve(P2, np.float32), np.float32)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("P", [W.maze_3d(48), W.layered_3d(40), W.random_problem(3100, 3, 30, zero_frac=0.15),
+                               W.maze_3d(24, seed=9)], ids=lambda P: P.name)
+def test_early_remedy_keeps_the_fixed_point(P, dtype):
+    """3D tile variant with and without the early remedy visits that idle
+    workgroups run during the update step: both meet the gate against the
+    oracle; the early visits are counted only when they ran (float32 3D, not
+    with early=False)."""
+    ref = ref_solve(P, dtype)
+    got_on, st_on = gpu_solve(P, dtype, variant="tile")
+    got_off, st_off = gpu_solve(P, dtype, variant="tile", early=False)
+    print(f"[stats] early evals {st_on['evals_early']} remedy evals on/off {st_on['evals_remedy']}/"
+          f"{st_off['evals_remedy']}", flush=True)
+    assert_close(got_on, ref, dtype)
+    assert_close(got_off, ref, dtype)
+    assert st_off["evals_early"] == 0
+    if dtype == np.float64:
+        assert st_on["evals_early"] == 0
+    elif P.name.startswith("maze_3d_48"):
+        assert st_on["evals_early"] > 0
+
+
+def test_no_early_remedy_in_2d():
+    P = W.lognormal_2d(200, seed=4)
+    got, st = gpu_solve(P, np.float32, variant="tile", tile=(16, 16))
+    assert_close(got, ref_solve(P, np.float32), np.float32)
+    assert st["evals_early"] == 0
