@@ -726,7 +726,9 @@ int eo_fim(int ndim, const int64_t* dims, double h, const double* F,
  * lambda = g + M^T lambda is solved downwind-to-upwind (decreasing phi).
  */
 
-static const double* g_sort_key;
+/* qsort's comparator reads the values through this pointer; one per thread,
+ * so that callers may run the adjoint of different grids concurrently. */
+static _Thread_local const double* g_sort_key;
 static int cmp_desc(const void* x, const void* y) {
     double a = g_sort_key[*(const int64_t*)x], b = g_sort_key[*(const int64_t*)y];
     if (a > b) return -1;

@@ -120,3 +120,25 @@ def test_adjoint_state_linearity_and_gradient():
     m = np.abs(l1) > 1e-6
     m.flat[P.sources] = False
     np.testing.assert_allclose(d1[m] / l1[m], d2[m] / l2[m], rtol=1e-9)
+
+
+def test_adjoint_threads_match_serial():
+    """The oracle's adjoint is called from thread pools (the batch baseline):
+    concurrent calls on grids of different sizes give the serial results."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(11)
+    probs = []
+    for _ in range(16):
+        n, m = int(rng.integers(16, 120)), int(rng.integers(16, 120))
+        F = np.exp(0.3 * rng.normal(size=(n, m)))
+        probs.append((F, np.array([int(rng.integers(0, n * m))])))
+
+    def one(P):
+        F, src = P
+        p = oracle.fmm(F, 1.0, src)
+        return oracle.adjoint(F, 1.0, src, p, np.ones(F.shape))
+    serial = [one(P) for P in probs]
+    for _ in range(3):
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            par = list(ex.map(one, probs))
+        assert all(np.array_equal(a, b) for a, b in zip(serial, par))
