@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
     __shared__ int s_stop;
     const T inf = pos_inf<T>();
     const uint32_t ntag = launch_tag(a);
-    const bool early = e.done != nullptr;
+    // early remedy visits exist in 3D float only (compiled out elsewhere)
+    const bool early = ND == 3 && sizeof(T) == 4 && e.done != nullptr;
     if (early) {
         __builtin_amdgcn_s_setprio(2);
         if (blockIdx.x == 0 && threadIdx.x < kSub) {
