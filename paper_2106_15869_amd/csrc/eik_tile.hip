@@ -13,7 +13,9 @@
 //     value no longer moves (phi - phi~ <= eps) converges and activates its FAR
 //     neighbours -- no convergence check of those neighbours (Section 3.3).
 //     A node converging on a tile face schedules the tile across that face; a
-//     tile that still holds active nodes schedules itself.
+//     tile that still holds active nodes schedules itself.  In 3D the
+//     workgroups that find no update tile in a launch run early remedy
+//     visits (below) on tiles whose update work is done.
 //   remedy detection (STEP 3, first part): one dense pass over all tiles;
 //     a tile with any node whose phi~ < phi - eps enters the remedy list.
 //   remedy loop (STEP 3): the remedy rule of Section 3.1.2 restricted to the
