@@ -139,6 +139,38 @@ def test_graph_capture_replays(variant):
         assert np.max(np.abs(got - ref)) <= 1e-12 * ref.max(), (rep, float(junk))
 
 
+def test_graph_capture_replays_3d_with_early_remedy():
+    """3D float32 solve (early remedy visits in the update step) enqueued with
+    async_=True and captured in a graph: every replay, with eager work in
+    between, meets the float32 gate and reports that its loops emptied."""
+    P = W.maze_3d(40, seed=3)
+    F = torch.from_numpy(P.F).to(DEV)
+    out = torch.empty_like(F)
+    ws = torch.empty(eik.eik_workspace_size(P.F.shape, eik.make_options(eik.EIK_FLOAT32, "tile")),
+                     dtype=torch.uint8, device=DEV)
+    _, st = eik.solve(F, P.h, P.sources, stats=True)
+    assert st["evals_early"] > 0
+    cap = int(1.25 * max(st["step2_iters"], st["step3_iters"])) + 32
+    ref = oracle.fmm(P.F.astype(np.float64), P.h, P.sources)
+    eik.solve(F, P.h, P.sources, out=out, workspace=ws, max_iters=cap, async_=True)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            eik.solve(F, P.h, P.sources, out=out, workspace=ws, max_iters=cap, async_=True, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(-1.0)
+        junk = torch.randn(1 << 16, device=DEV).sum()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        eik.check_async(ws)
+        got = out.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-5 * ref.max(), (rep, float(junk))
+
+
 @pytest.mark.parametrize("P", [W.lognormal_2d(300, seed=4), W.maze_3d(48)], ids=lambda P: P.name)
 def test_tune_picks_a_candidate_and_caches_it(P):
     """eik_tune times the shapes, then the ordered remedy's per-launch minimum
