@@ -411,15 +411,16 @@ def eik_adjoint_workspace_size(shape: Sequence[int], opt: Optional[EikOptions] =
 
 def adjoint(F, phi, h: Optional[float], sources, dL_dphi, out=None, workspace=None, stats: bool = False,
             stream=None, profile: bool = False, async_: bool = False, max_iters: int = 0,
-            spacing: Optional[Sequence[float]] = None):
-    """dL/dF at the converged solution phi (same F, h, sources).  async_ as in
-    solve()."""
+            spacing: Optional[Sequence[float]] = None, order_min: int = 0, workgroups: int = 0):
+    """dL/dF at the converged solution phi (same F, h, sources).  async_,
+    order_min and workgroups as in solve()."""
     torch = _torch()
     for t, n in ((F, "F"), (phi, "phi"), (dL_dphi, "dL_dphi")):
         _check_device_tensor(t, n)
         if t.shape != F.shape or t.dtype != F.dtype:
             raise ValueError(f"{n} must match F in shape and dtype")
-    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile, spacing=spacing)
+    opt = make_options(_dtype_code(F), max_iters=max_iters, async_=async_, profile=profile, spacing=spacing,
+                       order_min=order_min, workgroups=workgroups)
     h = 1.0 if h is None and spacing is not None else h
     if async_ and (workspace is None or out is None):
         raise ValueError("async_ needs a preallocated workspace and out")
