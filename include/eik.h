@@ -340,7 +340,7 @@ eik_status eik_async_status(const void* workspace, void* stream);
  *   (EIK_ERR_UNSUPPORTED): the call is synchronous.
  * Errors as eik_solve, and EIK_ERR_OUT_OF_MEMORY, before any device work,
  * when eik_workspace_size for the shape and options exceeds 128 MiB (e.g.
- * the tile variant takes 89 MiB at 256^3 and 98 MiB at 4096^2 in float32;
+ * the tile variant takes 90 MiB at 256^3 and 98 MiB at 4096^2 in float32;
  * the node-list variants need about 60 bytes per node and fit up to about
  * 2 M nodes).
  * Every call on one GPU shares that GPU's array, which keeps the last

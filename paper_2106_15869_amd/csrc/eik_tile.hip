@@ -215,7 +215,6 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
     // early remedy visits exist in 3D float only (compiled out elsewhere)
     const bool early = ND == 3 && sizeof(T) == 4 && e.done != nullptr;
     if (early) {
-        __builtin_amdgcn_s_setprio(2);
         if (blockIdx.x == 0 && threadIdx.x < kSub) {
             e.zero_count[threadIdx.x * kPad] = 0;
             e.zero_fetch[threadIdx.x * kPad] = 0;
@@ -440,7 +439,6 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
     // remedy after the update step (detection over every node, then the
     // ordered loop) still decides the fixed point.
     if (!early || visits) return;
-    __builtin_amdgcn_s_setprio(0);  // below the update visits still running on this CU
     const int elen = s_elen[k];
     unsigned long long eevals = 0;
     for (;;) {
