@@ -34,8 +34,11 @@ std::map<TuneKey, Choice>& tune_cache() {
     return m;
 }
 
-// Flags that change what a tile solve does (and so which shape is fastest).
+// Flags that change what a tile solve does (and so which shape is fastest);
+// with these the remedy is not ordered, so its per-launch minimum is not searched.
 constexpr uint32_t kScheduleFlags = EIK_FLAG_SKIP_REMEDY | EIK_FLAG_FIFO_REMEDY;
+// Flags a cached choice belongs to.
+constexpr uint32_t kCacheFlags = kScheduleFlags | EIK_FLAG_NO_EARLY_REMEDY;
 
 // A zero tile is the library default: in 2D that runs the update step on
 // 32 x 32 tiles and detection/remedy on 16 x 16, a pairing no explicit shape
@@ -107,7 +110,7 @@ EIK_API eik_status eik_tune(const void* F, int32_t ndim, const int64_t* dims, do
     for (int k = 0; k < 3; ++k) aniso |= opt->spacing[k] != 0.0;
     const TuneKey key = std::make_tuple(static_cast<int>(ndim), static_cast<int>(opt->dtype),
                                         static_cast<int>(std::floor(std::log2(static_cast<double>(n)))),
-                                        static_cast<int>(aniso), opt->flags & kScheduleFlags);
+                                        static_cast<int>(aniso), opt->flags & kCacheFlags);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = tune_cache().find(key);
