@@ -181,11 +181,159 @@ __device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& 
 
 
 // ---------------------------------------------------------------------------
+// A remedy visit (shared by the remedy launches and, in 3D, the early remedy
+// visits of the update step)
+// ---------------------------------------------------------------------------
+// LDS of a remedy visit.
+template <typename T, int NT>
+struct RemedyLds {
+    T* sphi;           // values with the one-cell halo
+    T* sH;             // the tile's cell values
+    TileLists<NT>* tl;
+    uint32_t* mask;    // dirty faces the visit starts from
+    int* face;         // faces a drop crossed
+    int* evals;        // local-solver evaluations
+    uint32_t* kmin;    // ordered: key of the smallest value that crossed a face (kNoKey before the visit)
+    int* stop;         // POLL: lane 0's stop answer
+    int* written;      // values written back, or null (not counted)
+};
+
+// The remedy rule on tile t at (x0, y0, z0): stage its values with the halo
+// and its cell values, list the free nodes to recheck (all of them for
+// kAllFaces in the dirty faces, else those on the dirty faces), and iterate
+// until the list is empty, `inner` iterations ran or (POLL) stop(), asked by
+// lane 0 every other iteration, said so (pending: nodes were still listed).
+// The dirty faces are *s.mask, or lane 0's mask_in when set_mask.  Leaves the
+// new values in sphi with tl->dirty set for the changed nodes, and the
+// crossed faces, evaluations and (ordered) the crossing key in LDS.  Returns
+// the iterations run.
+template <typename T, int ND, int TX, int TY, int TZ, bool AN, bool POLL, typename Stop>
+__device__ __forceinline__ int remedy_visit(const T* cells, const T* phi, const Inst<T>& g, int t, int x0, int y0,
+                                            int z0, int open, T eps, int inner, bool ordered, uint32_t mask_in,
+                                            bool set_mask, const RemedyLds<T, Shape<ND, TX, TY, TZ>::NT>& s,
+                                            bool& pending, Stop stop) {
+    using S = Shape<ND, TX, TY, TZ>;
+    const T inf = pos_inf<T>();
+    TileLists<S::NT>& tl = *s.tl;
+    T* sphi = s.sphi;
+    T hv[S::NPT];
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
+        hv[r] = cells[static_cast<size_t>(t) * S::NT + nn];
+    }
+    stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, phi, nullptr, sphi, nullptr);
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        const int nn = threadIdx.x + r * kBlock;
+        if (nn < S::NT) {
+            s.sH[nn] = hv[r];
+            tl.flag[0][nn] = 0u;
+            tl.flag[1][nn] = 0u;
+            tl.dirty[nn] = 0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        *s.face = 0;
+        *s.evals = 0;
+        if (s.written) *s.written = 0;
+        if (POLL) *s.stop = 0;
+        if (set_mask) *s.mask = mask_in;
+        tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
+    }
+    __syncthreads();
+    // initial remedy list: every non-source node on a first visit, else the
+    // nodes on the faces whose neighbour tile changed (barrier cells and
+    // nodes outside the grid have H = +inf and never change)
+    const uint32_t m = *s.mask;
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        const int nn = threadIdx.x + r * kBlock;
+        if (nn >= S::NT) continue;
+        int x, y, z, L;
+        node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+        const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
+        if (cell_free<T, AN>(s.sH[nn]) && ((m & kAllFaces) || (E & static_cast<int>(m))))
+            tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
+    }
+    __syncthreads();
+    pending = false;
+    int my_evals = 0, fm = 0;
+    T kmin = inf;  // smallest value that crossed a face (order key of the pushes)
+    int it = 0;
+    for (;; ++it) {
+        const int ncur = tl.cnt[it % 3];
+        if (ncur == 0) break;
+        if (it == inner || (POLL && *s.stop)) {
+            pending = true;
+            break;
+        }
+        const int cb = it & 1, nb = cb ^ 1;
+        int* ncnt = &tl.cnt[(it + 1) % 3];
+        if (threadIdx.x == 0) {
+            tl.cnt[(it + 2) % 3] = 0;
+            if (POLL && (it & 1)) *s.stop = stop() ? 1 : 0;
+        }
+        for (int i = threadIdx.x; i < ncur; i += kBlock) {
+            const int q = tl.list[cb][i];
+            tl.flag[cb][q] = 0u;
+            int x, y, z, Lq;
+            node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
+            ++my_evals;
+            const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, s.sH[q], g);
+            if (pt < sphi[Lq] - eps) {
+                sphi[Lq] = pt;
+                tl.dirty[q] = 1;
+                const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
+#pragma unroll
+                for (int d = 0; d < 2 * ND; ++d) {
+                    const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
+                    if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
+                    if (edge & (1 << d)) {
+                        if (open & (1 << d)) {
+                            fm |= 1 << d;
+                            kmin = tmin(kmin, pt);
+                        }
+                    } else {
+                        const int qn = q + node_step<TX, TY>(d);
+                        if (cell_free<T, AN>(s.sH[qn])) list_add(tl, nb, ncnt, qn);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (fm) atomicOr(s.face, fm);
+    if (my_evals) atomicAdd(s.evals, my_evals);
+    if (ordered && kmin < inf) atomicMin(s.kmin, order_key(kmin));
+    __syncthreads();
+    return it;
+}
+
+// Write back the values a remedy visit changed (and count them).
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void remedy_write_back(T* phi, const Inst<T>& g, int x0, int y0, int z0,
+                                                  const RemedyLds<T, Shape<ND, TX, TY, TZ>::NT>& s) {
+    using S = Shape<ND, TX, TY, TZ>;
+    int my_written = 0;
+#pragma unroll
+    for (int r = 0; r < S::NPT; ++r) {
+        const int nn = threadIdx.x + r * kBlock;
+        if (nn >= S::NT || !s.tl->dirty[nn]) continue;
+        int x, y, z, L;
+        node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
+        phi[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = s.sphi[L];
+        ++my_written;
+    }
+    if (s.written && my_written) atomicAdd(s.written, my_written);
+}
+
+// ---------------------------------------------------------------------------
 // STEP 2 on tiles
 // ---------------------------------------------------------------------------
 // Resident workgroups per CU for the update step: six for 8^3 float tiles
 // (two nodes per lane), so that all 1536 default workgroups of a launch are
-// resident at once (eighty registers, no spills); with early remedy visits a
+// resident at once (eighty registers, one value spilled); with early remedy visits a
 // workgroup that waited for a slot would start its visit late and hold the
 // launch.  Others unconstrained.
 template <int ND, int NPT, typename T>
@@ -462,86 +610,12 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
         const int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * (ND == 3 ? TZ : 1);
         const int open = open_bits<ND, TX, TY, TZ>(g, x0, y0, z0);
-        T hv[S::NPT];
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
-            hv[r] = e.cells[static_cast<size_t>(t) * S::NT + nn];
-        }
-        stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, a.phi, nullptr, sphi, nullptr);
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn < S::NT) {
-                sH[nn] = hv[r];
-                tl.flag[0][nn] = 0u;
-                tl.flag[1][nn] = 0u;
-                tl.dirty[nn] = 0;
-            }
-        }
-        if (threadIdx.x == 0) {
-            s_face = 0;
-            s_evals = 0;
-            s_stop = 0;
-            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
-        }
-        __syncthreads();
-        const uint32_t m = s_emask;
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn >= S::NT) continue;
-            int x, y, z, L;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-            const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
-            if (cell_free<T, AN>(sH[nn]) && ((m & kAllFaces) || (E & static_cast<int>(m))))
-                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
-        }
-        __syncthreads();
-        bool pending = false;
-        int my_evals = 0, fm = 0;
-        for (int it = 0;; ++it) {
-            const int ncur = tl.cnt[it % 3];
-            if (ncur == 0) break;
-            if (it == early_inner || s_stop) {  // the launch's update visits are done
-                pending = true;
-                break;
-            }
-            const int cb = it & 1, nb = cb ^ 1;
-            int* ncnt = &tl.cnt[(it + 1) % 3];
-            if (threadIdx.x == 0) {
-                tl.cnt[(it + 2) % 3] = 0;
-                if (it & 1) s_stop = __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n;
-            }
-            for (int i = threadIdx.x; i < ncur; i += kBlock) {
-                const int q = tl.list[cb][i];
-                tl.flag[cb][q] = 0u;
-                int x, y, z, Lq;
-                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
-                ++my_evals;
-                const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
-                if (pt < sphi[Lq] - eps) {
-                    sphi[Lq] = pt;
-                    tl.dirty[q] = 1;
-                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
-#pragma unroll
-                    for (int d = 0; d < 2 * ND; ++d) {
-                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                        if (!(pt < sphi[Ln])) continue;
-                        if (edge & (1 << d)) {
-                            if (open & (1 << d)) fm |= 1 << d;
-                        } else {
-                            const int qn = q + node_step<TX, TY>(d);
-                            if (cell_free<T, AN>(sH[qn])) list_add(tl, nb, ncnt, qn);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (fm) atomicOr(&s_face, fm);
-        if (my_evals) atomicAdd(&s_evals, my_evals);
-        __syncthreads();
+        const RemedyLds<T, S::NT> rl{sphi, sH, &tl, &s_emask, &s_face, &s_evals, nullptr, &s_stop, nullptr};
+        bool pending;
+        // stop once the launch's update visits are all done
+        remedy_visit<T, ND, TX, TY, TZ, AN, true>(
+            e.cells, a.phi, g, t, x0, y0, z0, open, eps, early_inner, false, 0u, false, rl, pending,
+            [&] { return __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n; });
         // a face whose neighbour tile is done with its update work marks that
         // tile; the others get their first visit when they are done
         if (threadIdx.x < 7) {
@@ -559,14 +633,7 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
                 }
             }
         }
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn >= S::NT || !tl.dirty[nn]) continue;
-            int x, y, z, L;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-            a.phi[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = sphi[L];
-        }
+        remedy_write_back<T, ND, TX, TY, TZ>(a.phi, g, x0, y0, z0, rl);
         if (threadIdx.x == 0) eevals += static_cast<unsigned long long>(s_evals);
         __syncthreads();
         break;  // one early visit per workgroup and launch: the launch ends with its update visits
@@ -651,7 +718,6 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
     __shared__ int s_written;
     __shared__ uint32_t s_mask;
     __shared__ uint32_t s_key, s_kmin;
-    const T inf = pos_inf<T>();
     const uint32_t ntag = launch_tag(a);
     // ordered mode: k_tile_split has moved this launch's tiles into the work
     // list (the rest went on to the next list)
@@ -699,93 +765,11 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
             }
             s_kmin = kNoKey;
         }
-        T hv[S::NPT];
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = min(static_cast<int>(threadIdx.x) + r * kBlock, S::NT - 1);
-            hv[r] = a.cells[static_cast<size_t>(t) * S::NT + nn];
-        }
-        stage<T, ND, TX, TY, TZ, false, false>(g, x0, y0, z0, a.phi, nullptr, sphi, nullptr);
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn < S::NT) {
-                sH[nn] = hv[r];
-                tl.flag[0][nn] = 0u;
-                tl.flag[1][nn] = 0u;
-                tl.dirty[nn] = 0;
-            }
-        }
-        if (threadIdx.x == 0) {
-            s_face = 0;
-            s_evals = 0;
-            s_written = 0;
-            if (!from_work) s_mask = mask_in;
-            tl.cnt[0] = tl.cnt[1] = tl.cnt[2] = 0;
-        }
-        __syncthreads();
-        // initial remedy list: every non-source node on a first visit, else the
-        // nodes on the faces whose neighbour tile changed (barrier cells and
-        // nodes outside the grid have H = +inf and never change)
-        const uint32_t m = s_mask;
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn >= S::NT) continue;
-            int x, y, z, L;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-            const int E = edge_bits<ND, TX, TY, TZ>(x, y, z) & open;
-            if (cell_free<T, AN>(sH[nn]) && ((m & kAllFaces) || (E & static_cast<int>(m))))
-                tl.list[0][atomicAdd(&tl.cnt[0], 1)] = static_cast<uint16_t>(nn);
-        }
-        __syncthreads();
-        bool pending = false;
-        int my_evals = 0, fm = 0;
-        T kmin = inf;  // smallest value that crossed a face (order key of the pushes)
-        int it = 0;
-        for (;; ++it) {
-            const int ncur = tl.cnt[it % 3];
-            if (ncur == 0) break;
-            if (it == inner) {
-                pending = true;
-                break;
-            }
-            const int cb = it & 1, nb = cb ^ 1;
-            int* ncnt = &tl.cnt[(it + 1) % 3];
-            if (threadIdx.x == 0) tl.cnt[(it + 2) % 3] = 0;
-            for (int i = threadIdx.x; i < ncur; i += kBlock) {
-                const int q = tl.list[cb][i];
-                tl.flag[cb][q] = 0u;
-                int x, y, z, Lq;
-                node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
-                ++my_evals;
-                const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, sH[q], g);
-                if (pt < sphi[Lq] - eps) {
-                    sphi[Lq] = pt;
-                    tl.dirty[q] = 1;
-                    const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
-#pragma unroll
-                    for (int d = 0; d < 2 * ND; ++d) {
-                        const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                        if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
-                        if (edge & (1 << d)) {
-                            if (open & (1 << d)) {
-                                fm |= 1 << d;
-                                kmin = tmin(kmin, pt);
-                            }
-                        } else {
-                            const int qn = q + node_step<TX, TY>(d);
-                            if (cell_free<T, AN>(sH[qn])) list_add(tl, nb, ncnt, qn);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (fm) atomicOr(&s_face, fm);
-        if (my_evals) atomicAdd(&s_evals, my_evals);
-        if (a.ordered && kmin < inf) atomicMin(&s_kmin, order_key(kmin));
-        __syncthreads();
+        const RemedyLds<T, S::NT> rl{sphi, sH, &tl, &s_mask, &s_face, &s_evals, &s_kmin, nullptr, &s_written};
+        bool pending;
+        const int it = remedy_visit<T, ND, TX, TY, TZ, AN, false>(a.cells, a.phi, g, t, x0, y0, z0, open, eps, inner,
+                                                                  a.ordered, mask_in, !from_work, rl, pending,
+                                                                  [] { return false; });
         // scheduling, one lane per target tile (see the update kernel); the
         // targets are read by the next launch, so these atomics may overlap
         // the write-back below
@@ -804,17 +788,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
                 push_keyed(a, tn, ntag, key);
             }
         }
-        int my_written = 0;
-#pragma unroll
-        for (int r = 0; r < S::NPT; ++r) {
-            const int nn = threadIdx.x + r * kBlock;
-            if (nn >= S::NT || !tl.dirty[nn]) continue;
-            int x, y, z, L;
-            node_loc<ND, TX, TY, TZ>(nn, x, y, z, L);
-            a.phi[g.node_base + ((z0 + z) * g.ny + (y0 + y)) * g.nx + (x0 + x)] = sphi[L];
-            ++my_written;
-        }
-        if (my_written) atomicAdd(&s_written, my_written);
+        remedy_write_back<T, ND, TX, TY, TZ>(a.phi, g, x0, y0, z0, rl);
         __syncthreads();
         if (threadIdx.x == 0) {
             evals += static_cast<unsigned long long>(s_evals);
