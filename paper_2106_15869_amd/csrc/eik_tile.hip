@@ -157,24 +157,38 @@ __device__ __forceinline__ void stage(const Inst<T>& g, int x0, int y0, int z0, 
     }
 }
 
-// G_i from the LDS tile (halo holds +inf outside the grid).
+// The neighbour values of LDS node L in direction order (-x, +x, -y, +y, -z, +z).
+template <typename T, int ND, int TX, int TY, int TZ>
+__device__ __forceinline__ void load_nb(const T* sphi, int L, T (&nb)[2 * ND]) {
+#pragma unroll
+    for (int d = 0; d < 2 * ND; ++d) nb[d] = sphi[L + lds_offset<ND, TX, TY, TZ>(d)];
+}
+
+// G_i from the neighbour values (+inf outside the grid).
 // v is the node's H = h / F (isotropic) or its speed F (AN: per-axis spacing,
 // H_k = spacing_k / F); see cell_value.
-template <typename T, int ND, int TX, int TY, int TZ, bool AN>
-__device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& g) {
-    using S = Shape<ND, TX, TY, TZ>;
+template <typename T, int ND, bool AN>
+__device__ __forceinline__ T eval_nb(const T (&nb)[2 * ND], T v, const Inst<T>& g) {
     const T inf = pos_inf<T>();
-    const T ax = tmin(sphi[L - 1], sphi[L + 1]);
-    const T ay = tmin(sphi[L - S::SY], sphi[L + S::SY]);
+    const T ax = tmin(nb[0], nb[1]);
+    const T ay = tmin(nb[2], nb[3]);
     if (AN) {
         if (!(v > T(0))) return inf;
         if (ND == 2) return godunov_aniso<T, 2>(ay, ax, inf, g.d[0] / v, g.d[1] / v, inf);
-        const T az = tmin(sphi[L - S::SZ], sphi[L + S::SZ]);
+        const T az = tmin(nb[4], nb[5]);
         return godunov_aniso<T, 3>(az, ay, ax, g.d[0] / v, g.d[1] / v, g.d[2] / v);
     }
     if (ND == 2) return godunov<T, 2>(ay, ax, inf, v);
-    const T az = tmin(sphi[L - S::SZ], sphi[L + S::SZ]);
+    const T az = tmin(nb[4], nb[5]);
     return godunov<T, 3>(az, ay, ax, v);
+}
+
+// G_i from the LDS tile (halo holds +inf outside the grid).
+template <typename T, int ND, int TX, int TY, int TZ, bool AN>
+__device__ __forceinline__ T eval_lds(const T* sphi, int L, T v, const Inst<T>& g) {
+    T nb[2 * ND];
+    load_nb<T, ND, TX, TY, TZ>(sphi, L, nb);
+    return eval_nb<T, ND, AN>(nb, v, g);
 }
 
 
@@ -280,23 +294,33 @@ __device__ __forceinline__ int remedy_visit(const T* cells, const T* phi, const 
             int x, y, z, Lq;
             node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
             ++my_evals;
-            const T pt = eval_lds<T, ND, TX, TY, TZ, AN>(sphi, Lq, s.sH[q], g);
-            if (pt < sphi[Lq] - eps) {
+            const T hq = s.sH[q];
+            T nv[2 * ND];
+            load_nb<T, ND, TX, TY, TZ>(sphi, Lq, nv);
+            const T pt = eval_nb<T, ND, AN>(nv, hq, g);
+            // a listed node that may not change (a fixed or barrier node
+            // appended by a neighbour) is skipped here
+            if (cell_free<T, AN>(hq) && pt < sphi[Lq] - eps) {
                 sphi[Lq] = pt;
                 tl.dirty[q] = 1;
+                // the new value reaches the neighbours above it; the values
+                // read for the solve are never below the current ones, so a
+                // neighbour that dropped meanwhile may be listed once more
+                // (an extra evaluation) but none is missed
+                int up = 0;
+#pragma unroll
+                for (int d = 0; d < 2 * ND; ++d) up |= pt < nv[d] ? 1 << d : 0;
                 const int edge = edge_bits<ND, TX, TY, TZ>(x, y, z);
 #pragma unroll
                 for (int d = 0; d < 2 * ND; ++d) {
-                    const int Ln = Lq + lds_offset<ND, TX, TY, TZ>(d);
-                    if (!(pt < sphi[Ln])) continue;  // not upwind of that neighbour
+                    if (!(up & (1 << d))) continue;
                     if (edge & (1 << d)) {
                         if (open & (1 << d)) {
                             fm |= 1 << d;
                             kmin = tmin(kmin, pt);
                         }
                     } else {
-                        const int qn = q + node_step<TX, TY>(d);
-                        if (cell_free<T, AN>(s.sH[qn])) list_add(tl, nb, ncnt, qn);
+                        list_add(tl, nb, ncnt, q + node_step<TX, TY>(d));
                     }
                 }
             }
