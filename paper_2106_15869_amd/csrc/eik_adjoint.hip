@@ -177,8 +177,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(AdjIter<T> a, BatchGeom<T> 
     }
 }
 
+// Resident workgroups per CU: six for 8^3 float tiles, so that all 1536
+// default workgroups of a launch are resident at once.  Others unconstrained.
+template <int ND, int NPT, typename T>
+constexpr int adj_blocks_per_cu() {
+    return ND == 3 && NPT == 2 && sizeof(T) == 4 ? 6 : 1;
+}
+
 template <typename T, int ND, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> bg, int inner) {
+__global__ __launch_bounds__(kBlock, (adj_blocks_per_cu<ND, Shape<ND, TX, TY, TZ>::NPT, T>())) void k_adj_tile(
+    AdjIter<T> a, BatchGeom<T> bg, int inner) {
     using S = Shape<ND, TX, TY, TZ>;
     __shared__ T slam[S::NL];
     __shared__ T scoef[3 * S::NL];
@@ -319,19 +327,31 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjIter<T> a, BatchGeom<T> 
                 int x, y, z, Lq;
                 node_loc<ND, TX, TY, TZ>(q, x, y, z, Lq);
                 // neighbour on the - side of axis k pulls into q if its upwind on
-                // axis k is its + side; on the + side, if its upwind is its - side
-                T v = sg[q];
+                // axis k is its + side; on the + side, if its upwind is its - side.
+                // Every neighbour's stencil byte, coefficient and value is read
+                // in one round (all inside the halo block), then summed in
+                // direction order.
                 const int offs[6] = {-1, 1, -SY, SY, -SZ, SZ};
+                uint32_t un[2 * ND];
+                T cn[2 * ND], ln[2 * ND];
+#pragma unroll
+                for (int d = 0; d < 2 * ND; ++d) {
+                    const int p = Lq + offs[d];
+                    un[d] = sup[p];
+                    cn[d] = scoef[3 * p + (d >> 1)];
+                    ln[d] = slam[p];
+                }
+                const T cur = slam[Lq];  // only this lane writes it in this iteration
+                T v = sg[q];
 #pragma unroll
                 for (int d = 0; d < 2 * ND; ++d) {
                     const int kx = d >> 1;
-                    const int p = Lq + offs[d];
-                    const uint32_t u = sup[p];
+                    const uint32_t u = un[d];
                     const bool present = (u & (1u << (2 * kx))) && !(u & kSrc);
                     const bool plus = (u >> (2 * kx + 1)) & 1u;
-                    if (present && plus == ((d & 1) == 0)) v = v + scoef[3 * p + kx] * slam[p];
+                    if (present && plus == ((d & 1) == 0)) v = v + cn[d] * ln[d];
                 }
-                if (v != slam[Lq]) {
+                if (v != cur) {
                     slam[Lq] = v;
                     tl.dirty[q] = 1;
                     // the nodes upwind of q pull from it: list them
