@@ -370,6 +370,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
             for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_next[j] = 0u;
         return;
     }
+    // this block's first entry, its key and dirty faces: loaded before the
+    // threshold so that both memory rounds are in flight together
+    int t0 = -1;
+    uint32_t key0 = kNoKey, mk0 = 0u;
+    {
+        const int e = blockIdx.x * kBlock + threadIdx.x;
+        if (e < n) {
+            int k = 0, i = e;
+            while (i >= s_len[k]) i -= s_len[k++];
+            t0 = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
+            key0 = a.key_cur[t0];
+            mk0 = a.mask_cur[t0];
+        }
+    }
     const int thr = order_threshold(a, n, &s_thr);
     // The deferred tiles are the listed tiles with key bins above thr, and
     // the current histogram counts the listed tiles by key bin, so the next
@@ -385,22 +399,26 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     __shared__ int s_base[2 * kSub];
     for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const int e = base + threadIdx.x;
-        int t = -1;
-        uint32_t key = kNoKey;
-        if (e < n) {
-            int k = 0, i = e;
-            while (i >= s_len[k]) i -= s_len[k++];
-            t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
-            key = a.key_cur[t];
+        int t = t0;
+        uint32_t key = key0, mk = mk0;
+        if (base != static_cast<int>(blockIdx.x) * kBlock) {
+            t = -1;
+            key = kNoKey;
+            mk = 0u;
+            if (e < n) {
+                int k = 0, i = e;
+                while (i >= s_len[k]) i -= s_len[k++];
+                t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
+                key = a.key_cur[t];
+                mk = a.mask_cur[t];
+            }
         }
         const bool now = t >= 0 && key_bin(key) <= thr;
         const bool defer = t >= 0 && !now;
-        uint32_t mk = 0u;
         if (t >= 0) {
             // the tile leaves the current list: its key and dirty faces go with
             // it (into the work entry, or on to the next list)
             a.key_cur[t] = kNoKey;
-            mk = a.mask_cur[t];
             a.mask_cur[t] = 0u;
         }
         if (defer) {
