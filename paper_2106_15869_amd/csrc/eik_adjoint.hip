@@ -453,7 +453,7 @@ eik_status adj_run(const Batch& b, const T* F, const T* phi, const T* g, T* out,
     const int inner = o.inner_iters > 0 ? o.inner_iters : 4 * (TX + TY + TZ);
     const int dense = static_cast<int>(std::min<int64_t>((b.n + kBlock - 1) / kBlock, 1 << 20));
     const int tiles = static_cast<int>(std::min<int64_t>(b.ntiles, 1 << 16));
-    const int split_blocks = static_cast<int>(std::min<int64_t>((b.ntiles + kBlock - 1) / kBlock, 1024));
+    const int split_blocks = split_blocks_of(b.ntiles);
     const size_t blk_bytes = 8 * static_cast<size_t>(kStatFields) * kMaxStatBlocks;
     int64_t launched = 0;
     Profiler prof;

@@ -354,14 +354,22 @@ __device__ __forceinline__ bool list_add(TileLists<NT>& tl, int nb, int* ncnt, i
 __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
     __shared__ int s_len[kSub];
     __shared__ int s_thr;
+    // Block b takes sub-list k = b % kSub, chunks b / kSub, b / kSub + G, ...
+    // of kBlock entries (G = gridDim.x / kSub; gridDim.x is a multiple of
+    // kSub), so its first entry is known before the list lengths and is
+    // loaded with them (an entry past the sub-list's length is not used).
+    const int k = blockIdx.x & (kSub - 1);
+    const int c0 = blockIdx.x / kSub;
+    const int i0 = c0 * kBlock + threadIdx.x;
+    const int t_first = i0 < a.cur.cap ? a.cur.data[static_cast<size_t>(k) * a.cur.cap + i0] : -1;
     if (threadIdx.x < kSub) s_len[threadIdx.x] = a.cur.count[threadIdx.x * kPad];
     __syncthreads();
     int n = 0;
 #pragma unroll
-    for (int k = 0; k < kSub; ++k) n += s_len[k];
-    // blocks past the list's end have nothing to do; an empty list stays
-    // empty (nothing is processed that could queue tiles)
-    if (n == 0 || (blockIdx.x > 0 && static_cast<int>(blockIdx.x) * kBlock >= n)) return;
+    for (int q = 0; q < kSub; ++q) n += s_len[q];
+    const int len = s_len[k];
+    // an empty list stays empty (nothing is processed that could queue tiles)
+    if (n == 0) return;
     // A list no longer than order_min goes to the launch whole: the consumer
     // then drains the current list itself (list_direct) and only the next
     // list's histogram has to start at zero.
@@ -370,48 +378,36 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
             for (int j = threadIdx.x; j < kBins; j += kBlock) a.hist_next[j] = 0u;
         return;
     }
-    // this block's first entry, its key and dirty faces: loaded before the
-    // threshold so that both memory rounds are in flight together
-    int t0 = -1;
-    uint32_t key0 = kNoKey, mk0 = 0u;
-    {
-        const int e = blockIdx.x * kBlock + threadIdx.x;
-        if (e < n) {
-            int k = 0, i = e;
-            while (i >= s_len[k]) i -= s_len[k++];
-            t0 = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
-            key0 = a.key_cur[t0];
-            mk0 = a.mask_cur[t0];
-        }
-    }
+    // blocks past their sub-list's end have nothing to do (the first kSub
+    // blocks stay: they write the next list's histogram)
+    if (blockIdx.x >= kSub && c0 * kBlock >= len) return;
+    // the first entry's key and dirty faces: loaded before the threshold so
+    // that both memory rounds are in flight together
+    const int t0 = i0 < len ? t_first : -1;
+    const uint32_t key0 = t0 >= 0 ? a.key_cur[t0] : kNoKey;
+    const uint32_t mk0 = t0 >= 0 ? a.mask_cur[t0] : 0u;
     const int thr = order_threshold(a, n, &s_thr);
     // The deferred tiles are the listed tiles with key bins above thr, and
     // the current histogram counts the listed tiles by key bin, so the next
     // list's histogram starts as its part above thr (the launch that adds to
-    // it runs after this one).  The active blocks share the bins.
-    const int nact = min(static_cast<int>(gridDim.x), (n + kBlock - 1) / kBlock);
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < kBins; j += nact * kBlock)
-        a.hist_next[j] = j > thr ? a.hist_cur[j] : 0u;
+    // it runs after this one).  The first kSub blocks share the bins.
+    if (blockIdx.x < kSub)
+        for (int j = blockIdx.x * kBlock + threadIdx.x; j < kBins; j += kSub * kBlock)
+            a.hist_next[j] = j > thr ? a.hist_cur[j] : 0u;
     // appends are counted per sub-list in LDS and reserved with one global
     // atomic per (list, sub-list) and block: thousands of waves hitting the
     // same list counters would otherwise queue behind each other
     __shared__ int s_cnt[2 * kSub];
     __shared__ int s_base[2 * kSub];
-    for (int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const int e = base + threadIdx.x;
+    const int chunks = static_cast<int>(gridDim.x) / kSub;
+    for (int c = c0; c * kBlock < len; c += chunks) {
+        const int i = c * kBlock + threadIdx.x;
         int t = t0;
         uint32_t key = key0, mk = mk0;
-        if (base != static_cast<int>(blockIdx.x) * kBlock) {
-            t = -1;
-            key = kNoKey;
-            mk = 0u;
-            if (e < n) {
-                int k = 0, i = e;
-                while (i >= s_len[k]) i -= s_len[k++];
-                t = a.cur.data[static_cast<size_t>(k) * a.cur.cap + i];
-                key = a.key_cur[t];
-                mk = a.mask_cur[t];
-            }
+        if (c != c0) {
+            t = i < len ? a.cur.data[static_cast<size_t>(k) * a.cur.cap + i] : -1;
+            key = t >= 0 ? a.key_cur[t] : kNoKey;
+            mk = t >= 0 ? a.mask_cur[t] : 0u;
         }
         const bool now = t >= 0 && key_bin(key) <= thr;
         const bool defer = t >= 0 && !now;
@@ -436,8 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
         __syncthreads();
         for (int j = threadIdx.x; j < 2 * kSub; j += kBlock) {
             const TList& L = j < kSub ? a.work : a.next;
-            const int k = j & (kSub - 1);
-            s_base[j] = s_cnt[j] ? atomicAdd(L.count + k * kPad, s_cnt[j]) : 0;
+            s_base[j] = s_cnt[j] ? atomicAdd(L.count + (j & (kSub - 1)) * kPad, s_cnt[j]) : 0;
         }
         __syncthreads();
         if (now || defer) {
@@ -457,6 +452,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_split(Sched a) {
 // Host side: workspace of the scheduling state and the per-launch arguments
 // ---------------------------------------------------------------------------
 constexpr size_t kCounterBytes = (3 * 2 * kSub * kPad + 3 * kBins) * sizeof(int);
+
+// Grid of k_tile_split: kSub blocks per chunk of kBlock entries of the
+// longest sub-list a list of ntiles tiles can hold (a tile is listed once,
+// in sub-list t % kSub), at most 128 chunks (blocks loop over the rest).
+inline int split_blocks_of(int64_t ntiles) {
+    const int64_t per_sub = (ntiles + kSub - 1) / kSub;
+    const int64_t chunks = (per_sub + kBlock - 1) / kBlock;
+    return kSub * static_cast<int>(chunks < 1 ? 1 : chunks > 128 ? 128 : chunks);
+}
 constexpr size_t kWorkCounterBytes = 2 * 2 * kSub * kPad * sizeof(int);
 
 struct SchedWs {

@@ -1257,7 +1257,7 @@ eik_status solve_tile(const Batch& b, const T* F, double eps, T* phi, const eik_
         gl += 1;
         launched += 2;
         int64_t n3 = 0;
-        const int split_blocks = static_cast<int>(std::min<int64_t>((b.ntiles + kBlock - 1) / kBlock, 1024));
+        const int split_blocks = split_blocks_of(b.ntiles);
         rc = run_loop(
             [&](int64_t t) {
                 const TileIter<T> a = iter_args(t, 1);
