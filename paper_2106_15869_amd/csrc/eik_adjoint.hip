@@ -199,6 +199,7 @@ __global__ __launch_bounds__(kBlock, (adj_blocks_per_cu<ND, Shape<ND, TX, TY, TZ
     __shared__ uint32_t s_mask, s_key, s_kmin;
     const uint32_t ntag = launch_tag(a);
     __shared__ int s_wlen[kSub];
+    const FirstEntry pre = first_entry(a, true);
     const int n = list_open(a, s_len, s_wlen);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) a.ctl->iters3 += 1;
     const bool direct = list_direct(a, n);  // a short list is drained where it is
@@ -212,12 +213,12 @@ __global__ __launch_bounds__(kBlock, (adj_blocks_per_cu<ND, Shape<ND, TX, TY, TZ
         if (threadIdx.x == 0) {
             const int e = fetch_index(src, k, len, first);
             const size_t idx = static_cast<size_t>(k) * src.cap + e;
-            const int tt = e < len ? src.data[idx] : -1;
+            const int tt = e < len ? (first ? (from_work ? pre.work : pre.cur) : src.data[idx]) : -1;
             if (tt >= 0) {
                 if (from_work) {
                     // the split moved the key and dirty faces into the work entry
-                    s_key = src.key[idx];
-                    s_mask = src.mask[idx];
+                    s_key = first ? pre.key : src.key[idx];
+                    s_mask = first ? pre.mask : src.mask[idx];
                 } else {
                     if (direct) {
                         s_key = a.key_cur[tt];
