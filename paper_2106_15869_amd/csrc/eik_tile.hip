@@ -215,17 +215,19 @@ struct RemedyLds {
 // The remedy rule on tile t at (x0, y0, z0): stage its values with the halo
 // and its cell values, list the free nodes to recheck (all of them for
 // kAllFaces in the dirty faces, else those on the dirty faces), and iterate
-// until the list is empty, `inner` iterations ran or (POLL) stop(), asked by
-// lane 0 every other iteration, said so (pending: nodes were still listed).
+// until the list is empty, `inner` iterations ran or (POLL) poll() reached
+// stop_at (pending: nodes were still listed).  Lane 0 issues poll() every
+// other iteration and reads its value one iteration later, so the load's
+// latency hides behind an iteration instead of holding the workgroup.
 // The dirty faces are *s.mask, or lane 0's mask_in when set_mask.  Leaves the
 // new values in sphi with tl->dirty set for the changed nodes, and the
 // crossed faces, evaluations and (ordered) the crossing key in LDS.  Returns
 // the iterations run.
-template <typename T, int ND, int TX, int TY, int TZ, bool AN, bool POLL, typename Stop>
+template <typename T, int ND, int TX, int TY, int TZ, bool AN, bool POLL, typename Poll>
 __device__ __forceinline__ int remedy_visit(const T* cells, const T* phi, const Inst<T>& g, int t, int x0, int y0,
                                             int z0, int open, T eps, int inner, bool ordered, uint32_t mask_in,
                                             bool set_mask, const RemedyLds<T, Shape<ND, TX, TY, TZ>::NT>& s,
-                                            bool& pending, Stop stop) {
+                                            bool& pending, Poll poll, int stop_at) {
     using S = Shape<ND, TX, TY, TZ>;
     const T inf = pos_inf<T>();
     TileLists<S::NT>& tl = *s.tl;
@@ -274,6 +276,7 @@ __device__ __forceinline__ int remedy_visit(const T* cells, const T* phi, const 
     pending = false;
     int my_evals = 0, fm = 0;
     T kmin = inf;  // smallest value that crossed a face (order key of the pushes)
+    int polled = 0;  // lane 0 (POLL): the value of the last poll()
     int it = 0;
     for (;; ++it) {
         const int ncur = tl.cnt[it % 3];
@@ -286,7 +289,10 @@ __device__ __forceinline__ int remedy_visit(const T* cells, const T* phi, const 
         int* ncnt = &tl.cnt[(it + 1) % 3];
         if (threadIdx.x == 0) {
             tl.cnt[(it + 2) % 3] = 0;
-            if (POLL && (it & 1)) *s.stop = stop() ? 1 : 0;
+            if (POLL) {
+                if (it & 1) polled = poll();
+                else if (it > 0) *s.stop = polled >= stop_at ? 1 : 0;
+            }
         }
         for (int i = threadIdx.x; i < ncur; i += kBlock) {
             const int q = tl.list[cb][i];
@@ -667,7 +673,7 @@ __global__ __launch_bounds__(kBlock, (update_blocks_per_cu<ND, Shape<ND, TX, TY,
         // stop once the launch's update visits are all done
         remedy_visit<T, ND, TX, TY, TZ, AN, true>(
             e.cells, a.phi, g, t, x0, y0, z0, open, eps, early_inner, false, 0u, false, rl, pending,
-            [&] { return __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n; });
+            [&] { return __hip_atomic_load(e.fin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }, n);
         // a face whose neighbour tile is done with its update work marks that
         // tile; the others get their first visit when they are done
         if (threadIdx.x < 7) {
@@ -821,7 +827,7 @@ __global__ __launch_bounds__(kBlock, (remedy_blocks_per_cu<Shape<ND, TX, TY, TZ>
         bool pending;
         const int it = remedy_visit<T, ND, TX, TY, TZ, AN, false>(a.cells, a.phi, g, t, x0, y0, z0, open, eps, inner,
                                                                   a.ordered, mask_in, !from_work, rl, pending,
-                                                                  [] { return false; });
+                                                                  [] { return 0; }, 0);
         // scheduling, one lane per target tile (see the update kernel); the
         // targets are read by the next launch, so these atomics may overlap
         // the write-back below
