@@ -123,6 +123,25 @@ def test_adjoint_matches_oracle(P, dtype):
     assert err.max() <= 1e-3 * np.max(np.abs(d_o)), (err.max() / np.max(np.abs(d_o)), int((~same).sum()))
 
 
+@pytest.mark.parametrize("order_min,workgroups", [(1, 8), (64, 1024)])
+@pytest.mark.parametrize("P", [W.lognormal_2d(96, seed=3), W.maze_3d(32)], ids=lambda P: P.name)
+def test_adjoint_schedule_options(P, order_min, workgroups):
+    """Small per-launch minimums send every adjoint launch with more tiles
+    than that through the split kernel and the work list (few or many
+    workgroups, each starting from its fixed first entry): node by node the
+    oracle's reverse sweep on the GPU's solution, float64 within 1e-9 of the
+    largest gradient."""
+    g = receiver_seed(P)
+    F = dev(P.F.astype(np.float64))
+    print(f"[case] adjoint {P.name} order_min {order_min} workgroups {workgroups}", flush=True)
+    phi = eik.solve(F, P.h, P.sources)
+    d = eik.adjoint(F, phi, P.h, P.sources, dev(g), order_min=order_min, workgroups=workgroups)
+    torch.cuda.synchronize()
+    phi_g = phi.cpu().numpy()
+    d_o = oracle.adjoint(P.F.astype(np.float64), P.h, P.sources, phi_g, g)
+    assert np.max(np.abs(d.cpu().numpy() - d_o)) <= 1e-9 * np.max(np.abs(d_o))
+
+
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])
 def test_euler_identity(dtype, tol):
     P = W.layered_3d(48, n_receivers=40)
