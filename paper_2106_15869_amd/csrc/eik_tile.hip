@@ -207,7 +207,7 @@ struct RemedyLds {
     uint32_t* mask;    // dirty faces the visit starts from
     int* face;         // faces a drop crossed
     int* evals;        // local-solver evaluations
-    uint32_t* kmin;    // ordered: key of the smallest value that crossed a face (kNoKey before the visit)
+    uint32_t* kmin;    // ordered: key of the smallest value that crossed a face (the caller sets kNoKey)
     int* stop;         // POLL: lane 0's stop answer
     int* written;      // values written back, or null (not counted)
 };
